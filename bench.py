@@ -1,0 +1,179 @@
+"""Benchmark: FFT fixed-point solvers for the 25% square array at 2048^2.
+
+One step = one full iteration of the solver (x pass with the local map and
+the fp64 reductions, finalize with the stop rules, Gamma pass with both
+y-direction FFTs) on the 2048 x 2048 grid.  The headline value is the
+voxel-iterations per second of the accelerated scheme (Eyre-Milton in H'',
+[alpha, beta] = [1/4, 4]) with complex-fp32 fields and fp64 reductions.
+The same line carries the sweep sigma1 in {10, 100, 1000, 0.01} x
+{MS, EM, ACC_EM} x {fp64 to 1e-8, fp32 to 1e-6}: iterations and device time
+to tolerance, sigma* and its error against eq. J47a, plus the roofline of
+the dominant kernel and the CPU oracle timed on a bounded sample.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 2048
+SIGMAS = (10.0, 100.0, 1000.0, 0.01)
+SCHEMES = ("ms", "em", "acc_em")
+HEADLINE = dict(scheme="acc_em", precision="fp32", sigma1=100.0)
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(scheme: str, precision: str, d: int, frac1: float):
+    """Bytes one voxel moves through HBM in each kernel of one iteration.
+
+    x pass: read + write the iterate (d complex), read + write the previous
+    physical field (d complex, for the relative increment), the phase byte,
+    and for the H'' schemes read + write of the S, T slots at phase-1 voxels
+    (2 slots for EM in H'', 1 for MS in H'').  Gamma pass: read + write the
+    iterate.  3D adds two plain y passes of the same size as the Gamma pass.
+    """
+    c = 8 if precision == "fp32" else 16
+    xp = 4 * d * c + 1
+    if scheme == "acc_em":
+        xp += 2 * 2 * d * c * frac1
+    elif scheme == "acc_ms":
+        xp += 2 * d * c * frac1
+    gp = 2 * d * c
+    return {"xpass": xp, "gamma": gp, "y": gp if d == 3 else 0.0}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-iters", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU slab decomposition is design-only)"}), flush=True)
+        return 2
+
+    import torch
+
+    from paper_2001_08289_amd import inputs
+    from paper_2001_08289_amd import scfft
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        return 1
+    torch.cuda.set_device(0)
+    chi_np = inputs.square_array(N)
+    chi = torch.as_tensor(chi_np).cuda()
+    frac1 = float(chi_np.mean())
+    e0 = (1.0, 0.0)
+    exact = {s: complex(np.sqrt((1 + 3 * s) / (3 + s))) for s in SIGMAS}   # eq. J47a
+
+    # ---------------------------------------------------------- headline
+    hs = HEADLINE
+    common = dict(alpha=0.25, beta=4.0, tol=-1.0, stag_window=0, div_factor=0.0,
+                  check_every=64, fields=False, history=False)
+    scfft.solve(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
+                max_iter=args.warmup, **common)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = scfft.solve(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
+                      max_iter=args.steps, **common)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = N * N * args.steps / wall
+    print(f"# headline {hs}: {args.steps} steps in {wall:.4f} s ({ms_per_step:.4f} ms/step), "
+          f"device loop {res['elapsed_ms']:.2f} ms", file=sys.stderr, flush=True)
+
+    # ---------------------------------------------------------- roofline
+    prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
+                                alpha=0.25, beta=4.0, iters=args.profile_iters)
+    ab = algorithmic_bytes(hs["scheme"], hs["precision"], 2, frac1)
+    kern = {k: {"ms": round(prof[k], 5),
+                "GB/s": round(ab[k] * N * N / (prof[k] * 1e-3) / 1e9, 1) if prof[k] > 0 else None}
+            for k in ("xpass", "gamma")}
+    dominant = max(("xpass", "gamma"), key=lambda k: prof[k])
+    achieved = ab[dominant] * N * N / (prof[dominant] * 1e-3) / 1e9
+    iter_bytes = (ab["xpass"] + ab["gamma"]) * N * N
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "bytes_per_launch": ab[dominant] * N * N,
+                "per_kernel": kern,
+                "iteration_GBps": round(iter_bytes / (ms_per_step * 1e-3) / 1e9, 1)}
+    print(f"# passes {prof}", file=sys.stderr, flush=True)
+
+    # ---------------------------------------------------------- sweep
+    sweep = []
+    if not args.no_sweep:
+        for prec, tol in (("fp64", 1e-8), ("fp32", 1e-6)):
+            for s1 in SIGMAS:
+                for scheme in SCHEMES:
+                    r = scfft.solve(chi, s1, e0, scheme, precision=prec, alpha=0.25, beta=4.0,
+                                    tol=tol, max_iter=3000, check_every=8, fields=False,
+                                    history=False, raise_on_error=False)
+                    row = {"precision": prec, "sigma1": s1, "scheme": scheme, "tol": tol,
+                           "status": r["status"], "iterations": r["iterations"],
+                           "time_ms": round(r["elapsed_ms"], 3),
+                           "sigma_star": r["sigma_star"].real,
+                           "rel_err_J47a": abs(r["sigma_star"] - exact[s1]) / abs(exact[s1])}
+                    sweep.append(row)
+                    print(f"# {row}", file=sys.stderr, flush=True)
+
+    def speedup(prec, s1):
+        t = {r["scheme"]: r["time_ms"] for r in sweep if r["precision"] == prec and r["sigma1"] == s1
+             and r["status"] == 0}
+        if "acc_em" not in t:
+            return None
+        return {"vs_ms": round(t["ms"] / t["acc_em"], 3) if "ms" in t else None,
+                "vs_em": round(t["em"] / t["acc_em"], 3) if "em" in t else None}
+
+    accel = {f"{p}@{s}": speedup(p, s) for p in ("fp64", "fp32") for s in SIGMAS} if sweep else {}
+
+    # ---------------------------------------------------------- CPU oracle
+    cpu = None
+    if not args.no_cpu:
+        from oracle import solver as osolver
+        t0 = time.perf_counter()
+        osolver.solve(chi_np, hs["sigma1"], [1.0, 0.0], hs["scheme"], alpha=0.25, beta=4.0, tol=-1,
+                      max_iter=1, stag_window=0, div_factor=0)
+        dt = time.perf_counter() - t0
+        cpu = {"value": N * N / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+               "sample": f"one iteration of the fp64 numpy oracle ({hs['scheme']}, 2048^2, own FFT), "
+                         f"{dt:.1f} s"}
+
+    out = {
+        "metric": "voxel-iters/s + time to 1e-8 residual, accelerated vs basic, FP32 vs FP64",
+        "value": value, "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 complex fields, fp64 reductions)",
+        "data": "synthetic",
+        "config": {"workload": "2D periodic square array of squares at 25% (centred square of side "
+                               "N/2), 2048x2048, e0 = e1; headline: accelerated scheme (EM in H'', "
+                               "[alpha,beta] = [1/4,4]) sigma1 = 100, complex-fp32 fields",
+                   "grid": [N, N], "sweep_sigma1": list(SIGMAS), "schemes": list(SCHEMES),
+                   "symbol": "rotated"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "speedup_time_to_tol": accel,
+        "sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,222 @@
+/*
+ * scfft -- FFT fixed-point solvers for periodic two-phase conducting
+ * composites on AMD Instinct MI355X (gfx950).
+ *
+ * The solvers follow G. W. Milton, "Substitution of subspace collections with
+ * nonorthogonal subspaces to accelerate Fast Fourier Transform methods
+ * applied to conducting composites":
+ *
+ *   SCFFT_MS      the basic Moulinec-Suquet scheme, series eq. J0-0,
+ *                 reference conductivity sigma0 = (sigma1 + 1)/2 (eq. J1);
+ *   SCFFT_EM      the Eyre-Milton scheme, expansion eq. J2,
+ *                 sigma0 = sqrt(sigma1);
+ *   SCFFT_ACC_EM  the paper's accelerated scheme: Eyre-Milton run in the
+ *                 substituted Hilbert space H'' (eqs. J27-J45, expansion
+ *                 eq. J43) with p set from the singularity interval
+ *                 [-beta, -alpha] by eq. J24 and t(sigma1) by eq. J23;
+ *   SCFFT_ACC_MS  Moulinec-Suquet run in H'' (expansion eq. J42a).
+ *
+ * The problem (eqs. J12-J13): on an N^d periodic voxel grid (d = 2, 3) with
+ * phase map chi (1 = inclusion of conductivity sigma1, 0 = matrix of
+ * conductivity sigma2 = 1) find E with <E> = e0, E - e0 curl free and
+ * J = sigma E divergence free; sigma* is reported as <J>.e0/|e0|^2
+ * (bilinear dot, real e0; a scalar for square/cubic symmetry, eq. J13).
+ * Gamma_1 = k k^T/|k|^2 (eq. J11) is evaluated with a discrete wavevector
+ * per DFT mode (SCFFT_GAMMA_*).
+ *
+ * Conventions for every entry point:
+ *   - grids: axis 0 (x) varies fastest; voxel (x, y, z) is at
+ *     x + n[0]*(y + n[1]*z); vector fields are component-major [d][N^d];
+ *     every n[i] must factor into 2, 3 and 5 and lie in [2, 4096];
+ *   - every pointer documented "device" is a device address on the current
+ *     HIP device, owned by the caller, and must stay valid until the call
+ *     returns; "host" pointers likewise; the library never frees them;
+ *   - the library owns only internal workspaces (state fields, reductions),
+ *     which it caches between calls and frees in scfft_release();
+ *   - all work is enqueued on options->stream (a hipStream_t, NULL = the
+ *     default stream) and the calls return after synchronising that stream;
+ *     calls from several host threads must use distinct streams and are
+ *     otherwise not re-entrant (the workspace cache is shared);
+ *   - a negative return value is an error (scfft_status); outputs are filled
+ *     on SCFFT_OK, SCFFT_ERR_NOT_CONVERGED, SCFFT_ERR_DIVERGED and
+ *     SCFFT_ERR_STAGNATED (with the last iterate).
+ */
+#ifndef SCFFT_H
+#define SCFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } scfft_c64;
+
+typedef enum {
+  SCFFT_MS = 0,
+  SCFFT_EM = 1,
+  SCFFT_ACC_EM = 2,
+  SCFFT_ACC_MS = 3
+} scfft_scheme;
+
+typedef enum {
+  SCFFT_FP64 = 0, /* fp64 complex fields and FFTs */
+  SCFFT_FP32 = 1  /* fp32 complex fields and FFTs; reductions, residual and
+                     scheme scalars stay fp64 */
+} scfft_precision;
+
+/* Discrete reading of Gamma_1 (eq. J11), theta_j = 2 pi m_j / n_j:
+ *  ROTATED  n_j = sin(theta_j/2) prod_{l != j} cos(theta_l/2); modes with
+ *           n = 0 but m != 0 use n_j = [m_j == n_j/2];
+ *  SPECTRAL the literal integer wavevector, m_j in (-n_j/2, n_j/2]; Nyquist
+ *           components are zeroed at modes that also have a non-zero
+ *           non-Nyquist component;
+ *  NETWORK  n_j = exp(i theta_j) - 1, used as n n^H/|n|^2.               */
+typedef enum {
+  SCFFT_GAMMA_ROTATED = 0,
+  SCFFT_GAMMA_SPECTRAL = 1,
+  SCFFT_GAMMA_NETWORK = 2
+} scfft_symbol;
+
+typedef enum {
+  SCFFT_OK = 0,
+  SCFFT_ERR_INVALID_ARG = -1,   /* bad size, pointer, scheme, interval ... */
+  SCFFT_ERR_SLIT = -2,          /* sigma1 where the scheme's expansion has no
+                                   meaning: on [-beta,-alpha] (H'' schemes),
+                                   on (-inf, 0] (SCFFT_EM) */
+  SCFFT_ERR_NOT_CONVERGED = -3, /* max_iter reached */
+  SCFFT_ERR_DIVERGED = -4,      /* non-finite values, or the residual grew past
+                                   div_factor times its running minimum */
+  SCFFT_ERR_STAGNATED = -5,     /* no new residual minimum for stag_window
+                                   consecutive iterations */
+  SCFFT_ERR_DEVICE = -6,        /* a HIP call failed */
+  SCFFT_ERR_OOM = -7            /* workspace allocation failed */
+} scfft_status;
+
+/* One solve's input. */
+typedef struct {
+  int d;                  /* 2 or 3 */
+  int n[3];               /* grid; n[2] ignored when d = 2 */
+  const uint8_t* phase;   /* device, N^d bytes: 1 = phase 1, 0 = matrix; used
+                             when density is NULL */
+  const double* density;  /* device, N^d doubles in [0, 1] or NULL: a graded
+                             medium sigma(x) = 1 + (sigma1 - 1) rho(x); only
+                             SCFFT_MS and SCFFT_EM accept it */
+  scfft_c64 sigma1;       /* inclusion conductivity (sigma2 = 1) */
+  double e0[3];           /* applied average field, real, not all zero */
+} scfft_problem;
+
+typedef struct {
+  int scheme;             /* scfft_scheme */
+  int precision;          /* scfft_precision */
+  int symbol;             /* scfft_symbol */
+  double alpha, beta;     /* H'' schemes: 0 < alpha < beta < inf */
+  int sigma0_set;         /* MS/EM: 1 = use sigma0 below instead of the default */
+  scfft_c64 sigma0;       /* reference conductivity override */
+  double tol;             /* stop at the first n >= 1 with r_n <= tol, where
+                             r_n = ||E^n - E^{n-1}|| / ||E^n|| over the physical
+                             field; tol < 0 runs exactly max_iter iterations */
+  int max_iter;           /* >= 0 */
+  int check_every;        /* host reads the device status every this many
+                             iterations (>= 1); does not change the result */
+  int stag_window;        /* 0 disables the stagnation stop */
+  double div_factor;      /* 0 disables the divergence-by-growth stop */
+  void* stream;           /* hipStream_t or NULL */
+} scfft_options;
+
+/* Fills *o with the defaults: ACC_EM, FP64, ROTATED, [alpha,beta] = [1/4,4],
+ * tol 1e-8, max_iter 1000, check_every 16, stag_window 20, div_factor 1e3. */
+void scfft_default_options(scfft_options* o);
+
+typedef struct {
+  scfft_c64* E;           /* device [d][N^d] or NULL: physical field E^n (the
+                             Q-slot of E'' for the H'' schemes) */
+  scfft_c64* J;           /* device [d][N^d] or NULL: sigma(x) E^n */
+  scfft_c64 sigma_star;   /* <sigma E^n>.e0/|e0|^2 */
+  scfft_c64 mean_J[3];    /* <sigma E^n> */
+  int iterations;         /* n of the returned iterate */
+  double residual;        /* r_n (NaN when n = 0) */
+  int status;             /* same as the return value */
+  double* residual_history;   /* host, history_cap entries, or NULL: r_0..r_n */
+  scfft_c64* sigma_history;   /* host, history_cap entries, or NULL */
+  int history_cap;
+  double elapsed_ms;      /* device time of the iteration loop (HIP events) */
+} scfft_result;
+
+/* Solve one problem (eqs. J12-J13) with one scheme. */
+scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt,
+                         scfft_result* res);
+
+/* Batched sweep: nprob microstructures (grids may differ) times nsig
+ * conductivities each.  sigma1s (host) holds nprob*nsig values, problem-major;
+ * opts (host) holds one options struct per problem (alpha, beta may differ;
+ * precision, symbol, tolerances and the stream are taken from opts[0]);
+ * results (host) receives nprob*nsig entries, problem-major (their E/J
+ * pointers, if set, must each hold one field).  Every solve keeps its own
+ * stop status; finished solves are skipped by the remaining iterations.
+ * prob[i].sigma1 is ignored.  Returns the worst status. */
+scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs,
+                               const scfft_options* opts, int nsig,
+                               const scfft_c64* sigma1s, scfft_result* results);
+
+/* Power-iteration estimate of the singularity interval: the spectrum of
+ * Gamma_1 chi Gamma_1 on curl-free fields lies in [mu_min, mu_max], and
+ * sigma*(sigma1) is singular at sigma1 = 1 - 1/mu, hence alpha = 1/mu_max - 1
+ * and beta = 1/mu_min - 1 (section "Estimating the parameters alpha and
+ * beta").  u_0 = e0, u_k = Gamma_1(w u_{k-1}) for k = 1..iters+1 with w = chi
+ * (then w = 1 - chi), Rayleigh quotient (u, w u)/(u, u) at the last u.  fp64.
+ * Outputs are host pointers (any may be NULL). */
+scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters,
+                                     int symbol, void* stream, double* alpha,
+                                     double* beta, double* mu_min,
+                                     double* mu_max);
+
+/* Gradient of sigma* by an adjoint solve.  Forward: SCFFT_EM (sigma0 =
+ * sqrt(sigma_min sigma_max) over the medium unless opt->sigma0_set).
+ * Adjoint: the transposed Eyre-Milton iteration m <- Z W m + c with
+ * W = I - 2 Gamma_1, Z = (sigma - sigma0)/(sigma + sigma0),
+ * c = sigma/(sigma + sigma0) e0, iterated on y = W m with the same kernels;
+ * then d sigma* / d sigma(x) = 2 sigma0/(sigma + sigma0)^2 (y.P + P.e0/2) /
+ * (N^d |e0|^2), P = (sigma + sigma0) E.
+ * Writes (each optional): g (device, N^d) = d sigma* / d sigma(x);
+ * drho (device, N^d) = (sigma1 - 1) g = d sigma* / d rho(x);
+ * dsigma1 (host) = sum_x g(x) rho(x) (rho = chi for a phase map).
+ * fwd/adj (host, optional) receive the two solves' reports. */
+scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
+                            scfft_c64* g, scfft_c64* drho, scfft_c64* dsigma1,
+                            scfft_result* fwd, scfft_result* adj);
+
+/* Average device duration (ms, HIP events on opt->stream) of each kernel of
+ * one iteration over `iters` iterations of the given solve configuration:
+ * ms[0] real-space x pass, ms[1] Gamma pass (last axis), ms[2] forward y pass
+ * (3D), ms[3] inverse y pass (3D), ms[4] status/reduction finalize.  The
+ * passes run the real iteration (status checks disabled).  cap >= 5. */
+scfft_status scfft_profile_passes(const scfft_problem* prob,
+                                  const scfft_options* opt, int iters,
+                                  double* ms, int cap);
+
+/* Scheme scalars (host fp64, no device use): out[] receives, as complex
+ * numbers, sigma0, t (eq. J23; 0 for MS/EM), z (the expansion variable of
+ * eqs. J1, J2, J42a or J4), p1, p2, p3 (eq. J24; 0 for MS/EM), E2' (eq. J21),
+ * J3' (eq. J26): 8 entries. */
+scfft_status scfft_scheme_scalars(int scheme, scfft_c64 sigma1, double alpha,
+                                  double beta, scfft_c64* out);
+
+/* sigma1 whose accelerated-scheme variable z (eq. J4) has the given value:
+ * the inverse of the slit map t of eq. J3 at t = ((1+z)/(1-z))^2. */
+scfft_c64 scfft_sigma1_from_z(double alpha, double beta, scfft_c64 z);
+
+/* Static description of a status code. */
+const char* scfft_status_string(int status);
+
+/* Frees every cached workspace on every device. */
+void scfft_release(void);
+
+/* Library version string. */
+const char* scfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCFFT_H */

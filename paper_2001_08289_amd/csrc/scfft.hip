@@ -1,0 +1,1039 @@
+// Host driver and C ABI of libscfft (see include/scfft.h).
+//
+// The host side only validates arguments, computes the scheme scalars in fp64
+// (slit map t of eq. J23, p of eq. J24, the expansion variables of eqs. J1,
+// J2, J4, J42a), owns cached device workspaces, and enqueues the kernels of
+// kernels.hpp; every per-voxel and per-mode operation runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "kernels.hpp"
+#include "scfft.h"
+
+using cd = std::complex<double>;
+
+namespace scfft {
+namespace {
+
+constexpr int kNT = 256;
+// elements a workgroup transforms at once (64 KiB of LDS in both precisions)
+constexpr int kElemsF32 = 8192;
+constexpr int kElemsF64 = 4096;
+
+#define SCFFT_HIP(call)                                                     \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      if (std::getenv("SCFFT_LOG"))                                         \
+        std::fprintf(stderr, "scfft: %s failed: %s (%s:%d)\n", #call,       \
+                     hipGetErrorString(e_), __FILE__, __LINE__);            \
+      return e_ == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;  \
+    }                                                                       \
+  } while (0)
+
+bool smooth235(int n) {
+  if (n < 2) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+FftDesc make_desc(int n) {
+  FftDesc fd{};
+  fd.n = n;
+  int m = n;
+  for (int r : {8, 4, 2, 3, 5}) {
+    while (m % r == 0) {
+      fd.radix[fd.npass++] = r;
+      m /= r;
+    }
+  }
+  return fd;
+}
+
+int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+
+struct Plan {
+  int dev = 0, d = 2, n[3] = {1, 1, 1}, prec = 0, nsolve = 1, symbol = 0;
+  bool st = false;
+  long long M = 0;
+  size_t esz = 16;
+  void* X = nullptr;
+  void* Ep = nullptr;
+  void* S = nullptr;
+  void* T = nullptr;
+  double* part = nullptr;
+  SolveCtl* ctl = nullptr;
+  SolveCoef* coef = nullptr;
+  double* hist_r = nullptr;
+  double* hist_s = nullptr;
+  int hist_cap = 0;
+  void* tw[3] = {nullptr, nullptr, nullptr};
+  double* sym[3] = {nullptr, nullptr, nullptr};
+  FftDesc fd[3];
+  int xlines = 0, xL = 1, xblocks = 0;
+  int gC = 1, yC = 1;
+};
+
+using PlanKey = std::tuple<int, int, int, int, int, int, int, bool, int, int>;
+std::map<PlanKey, Plan*> g_plans;
+std::mutex g_mutex;
+
+void free_plan(Plan* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->dev);
+  void* ptrs[] = {p->X, p->Ep, p->S, p->T, p->part, p->ctl, p->coef, p->hist_r, p->hist_s,
+                  p->tw[0], p->tw[1], p->tw[2], p->sym[0], p->sym[1], p->sym[2]};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+int elems_for(int prec) { return prec == SCFFT_FP32 ? kElemsF32 : kElemsF64; }
+
+// Size limits of the LDS-staged passes.
+scfft_status check_dims(int d, const int* n, int prec) {
+  if (d != 2 && d != 3) return SCFFT_ERR_INVALID_ARG;
+  for (int i = 0; i < d; ++i)
+    if (!smooth235(n[i]) || n[i] > 4096) return SCFFT_ERR_INVALID_ARG;
+  const int el = elems_for(prec);
+  if (n[0] > el) return SCFFT_ERR_INVALID_ARG;
+  if (n[d - 1] * d > el) return SCFFT_ERR_INVALID_ARG;
+  if (d == 3 && n[1] > el) return SCFFT_ERR_INVALID_ARG;
+  return SCFFT_OK;
+}
+
+scfft_status ensure_hist(Plan* p, int cap) {
+  if (cap <= p->hist_cap) return SCFFT_OK;
+  if (p->hist_r) (void)hipFree(p->hist_r);
+  if (p->hist_s) (void)hipFree(p->hist_s);
+  p->hist_r = nullptr;
+  p->hist_s = nullptr;
+  p->hist_cap = 0;
+  SCFFT_HIP(hipMalloc(&p->hist_r, sizeof(double) * (size_t)cap * p->nsolve));
+  SCFFT_HIP(hipMalloc(&p->hist_s, 2 * sizeof(double) * (size_t)cap * p->nsolve));
+  p->hist_cap = cap;
+  return SCFFT_OK;
+}
+
+// `slot` separates workspaces of same-shaped problems solved together.
+scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int symbol,
+                      hipStream_t stream, Plan** out, int slot = 0) {
+  int dev = 0;
+  SCFFT_HIP(hipGetDevice(&dev));
+  const int n2 = d == 3 ? n[2] : 1;
+  PlanKey key{dev, d, n[0], n[1], n2, prec, nsolve, st, symbol, slot};
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second;
+    return SCFFT_OK;
+  }
+  Plan* p = new Plan();
+  p->dev = dev;
+  p->d = d;
+  p->n[0] = n[0];
+  p->n[1] = n[1];
+  p->n[2] = n2;
+  p->prec = prec;
+  p->nsolve = nsolve;
+  p->st = st;
+  p->symbol = symbol;
+  p->M = (long long)n[0] * n[1] * n2;
+  p->esz = prec == SCFFT_FP32 ? 8 : 16;
+  const int el = elems_for(prec);
+  p->xlines = (int)(p->M / n[0]);
+  p->xL = std::max(1, std::min(el / n[0], p->xlines));
+  p->xblocks = (p->xlines + p->xL - 1) / p->xL;
+  const int nlast = n[d - 1];
+  p->gC = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
+  p->yC = d == 3 ? std::min(pow2_floor(std::max(1, el / n[1])), n[0]) : 1;
+  const size_t field = (size_t)nsolve * d * p->M * p->esz;
+  auto fail = [&](hipError_t e) {
+    free_plan(p);
+    return e == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&p->X, field)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&p->Ep, field)) != hipSuccess) return fail(e);
+  if (st) {
+    if ((e = hipMalloc(&p->S, field)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&p->T, field)) != hipSuccess) return fail(e);
+  }
+  if ((e = hipMalloc(&p->part, sizeof(double) * 5 * (size_t)nsolve * d * p->xblocks)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMalloc(&p->ctl, sizeof(SolveCtl) * nsolve)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&p->coef, sizeof(SolveCoef) * nsolve)) != hipSuccess) return fail(e);
+  for (int a = 0; a < d; ++a) {
+    p->fd[a] = make_desc(n[a]);
+    if ((e = hipMalloc(&p->tw[a], p->esz * n[a])) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&p->sym[a], 2 * sizeof(double) * n[a])) != hipSuccess) return fail(e);
+    const int blocks = (n[a] + 255) / 256;
+    if (prec == SCFFT_FP32)
+      hipLaunchKernelGGL(twiddle_kernel<float>, dim3(blocks), dim3(256), 0, stream,
+                         reinterpret_cast<cx<float>*>(p->tw[a]), n[a]);
+    else
+      hipLaunchKernelGGL(twiddle_kernel<double>, dim3(blocks), dim3(256), 0, stream,
+                         reinterpret_cast<cx<double>*>(p->tw[a]), n[a]);
+    hipLaunchKernelGGL(symbol_table_kernel, dim3(blocks), dim3(256), 0, stream, p->sym[a], n[a],
+                       symbol);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  }
+  if (ensure_hist(p, 64) != SCFFT_OK) {
+    free_plan(p);
+    return SCFFT_ERR_OOM;
+  }
+  g_plans[key] = p;
+  *out = p;
+  return SCFFT_OK;
+}
+
+// ------------------------------------------------------------- host scalars
+void put(double* dst, cd v) {
+  dst[0] = v.real();
+  dst[1] = v.imag();
+}
+
+struct Scalars {
+  cd sigma0, t, z, p[3], e2p, j3p;
+};
+
+// p from (alpha, beta): eq. J24 solved for p1^2, p2^2 with p^T p = 1.
+void p_from_interval(double a, double b, cd* p) {
+  const double w = b - a;
+  p[0] = std::sqrt(cd((1 + a) * (1 + b) / w, 0));
+  p[1] = std::sqrt(cd(-(1 + a) / w, 0));
+  p[2] = std::sqrt(cd(-a * (1 + b) / w, 0));
+}
+
+// t(sigma1) of eq. J3 / J23.
+cd t_map(cd s, double a, double b) { return (s + a) * (1.0 + b) / ((s + b) * (1.0 + a)); }
+
+scfft_status scheme_scalars(int scheme, cd s1, double a, double b, Scalars* out) {
+  Scalars r{};
+  if (scheme == SCFFT_ACC_EM || scheme == SCFFT_ACC_MS) {
+    if (!(a > 0.0 && b > a && std::isfinite(b))) return SCFFT_ERR_INVALID_ARG;
+    if (s1.imag() == 0.0 && s1.real() >= -b && s1.real() <= -a) return SCFFT_ERR_SLIT;
+    p_from_interval(a, b, r.p);
+    r.t = t_map(s1, a, b);
+    const cd w = std::sqrt(r.t);
+    if (scheme == SCFFT_ACC_EM) {
+      r.sigma0 = w;
+      r.z = (w - 1.0) / (w + 1.0);
+    } else {
+      r.sigma0 = (r.t + 1.0) / 2.0;
+      r.z = (r.t - 1.0) / (r.t + 1.0);
+    }
+    const cd den = (r.t - 1.0) * r.p[1] * r.p[1] + 1.0;
+    r.e2p = (1.0 - r.t) * r.p[0] * r.p[1] / den;    // eq. J21
+    r.j3p = r.p[0] * r.p[2] * (r.t - 1.0) / den;    // eq. J26
+  } else if (scheme == SCFFT_MS) {
+    r.sigma0 = (s1 + 1.0) / 2.0;
+    r.z = (s1 - 1.0) / (s1 + 1.0);                   // eq. J1
+  } else if (scheme == SCFFT_EM) {
+    if (s1.imag() == 0.0 && s1.real() <= 0.0) return SCFFT_ERR_SLIT;
+    r.sigma0 = std::sqrt(s1);
+    r.z = (r.sigma0 - 1.0) / (r.sigma0 + 1.0);       // eq. J2
+  } else {
+    return SCFFT_ERR_INVALID_ARG;
+  }
+  *out = r;
+  return SCFFT_OK;
+}
+
+// Fill the per-phase coefficient tables of a two-phase or graded medium.
+void fill_local(SolveCoef& c, int kind, cd s1, cd s0) {
+  const cd sig[2] = {cd(1, 0), s1};
+  for (int ph = 0; ph < 2; ++ph) {
+    const cd s = sig[ph];
+    cd cE(1, 0), cO, cJ = s, cS(0, 0);
+    if (kind == K_MS) {
+      cO = 1.0 - s / s0;
+    } else if (kind == K_EM) {
+      cE = 1.0 / (s + s0);
+      cO = (s - s0) / (s + s0);
+    } else if (kind == K_ADJ) {
+      cO = (s - s0) / (s + s0);
+      cJ = 0.0;
+      cS = s / (s + s0);
+    }
+    put(c.cE[ph], cE);
+    put(c.cO[ph], cO);
+    put(c.cJ[ph], cJ);
+    put(c.cS[ph], cS);
+  }
+  put(c.s1, s1);
+  put(c.s0, s0);
+}
+
+struct SolveSpec {
+  int kind;
+  cd s1, s0;
+  Scalars sc;
+  int power_phase;   // K_POWER: weight chi (1) or 1 - chi (0)
+};
+
+void fill_coef(SolveCoef& c, const SolveSpec& sp, bool density, int d, const double* e0, double M) {
+  std::memset(&c, 0, sizeof(c));
+  c.kind = sp.kind;
+  c.density = density ? 1 : 0;
+  cd src(0, 0), init(0, 0);   // multipliers of e0
+  switch (sp.kind) {
+    case K_MS:
+      fill_local(c, K_MS, sp.s1, sp.s0);
+      c.ga = 0;
+      c.gb = 1;
+      c.kz_keep = 0;
+      src = init = 1.0;
+      break;
+    case K_EM:
+      fill_local(c, K_EM, sp.s1, sp.s0);
+      c.ga = 1;
+      c.gb = -2;
+      c.kz_keep = 1;
+      src = init = 2.0 * sp.s0;
+      break;
+    case K_ADJ:
+      fill_local(c, K_ADJ, sp.s1, sp.s0);
+      c.ga = 1;
+      c.gb = -2;
+      c.kz_keep = 1;
+      break;
+    case K_POWER: {
+      for (int ph = 0; ph < 2; ++ph) {
+        const double w = (ph == sp.power_phase) ? 1.0 : 0.0;
+        put(c.cE[ph], 1.0);
+        put(c.cO[ph], w);
+        put(c.cJ[ph], w);
+        put(c.cS[ph], 0.0);
+      }
+      c.ga = 0;
+      c.gb = 1;
+      c.kz_keep = 0;
+      init = 1.0;
+      break;
+    }
+    case K_ACC_EM:
+    case K_ACC_MS: {
+      put(c.s1, sp.s1);
+      put(c.s0, sp.s0);
+      for (int i = 0; i < 3; ++i) put(c.p[i], sp.sc.p[i]);
+      put(c.z, sp.sc.z);
+      const cd w = std::sqrt(sp.sc.t);
+      put(c.inv1w, 1.0 / (1.0 + w));
+      put(c.p1kap, sp.sc.p[0] * (1.0 / (sp.sc.t + w) - 1.0 / (1.0 + w)));
+      if (sp.kind == K_ACC_EM) {
+        c.ga = 1;
+        c.gb = -2;
+        c.kz_keep = 1;
+        src = init = 2.0 * w;
+      } else {
+        c.ga = 0;
+        c.gb = 1;
+        c.kz_keep = 0;
+        src = init = 1.0;
+      }
+      break;
+    }
+  }
+  for (int i = 0; i < d; ++i) {
+    put(c.kz_src[i], src * (M * e0[i]));
+    put(c.init_src[i], init * (M * e0[i]));
+  }
+}
+
+void fill_ctl(SolveCtl& c, const scfft_options& o, int kind, int d, const double* e0) {
+  std::memset(&c, 0, sizeof(c));
+  c.tol = o.tol;
+  c.div_factor = o.div_factor;
+  c.max_iter = o.max_iter;
+  c.stag_window = o.stag_window;
+  double n2 = 0;
+  for (int i = 0; i < d; ++i) {
+    c.e0[i] = e0[i];
+    n2 += e0[i] * e0[i];
+  }
+  c.inv_e0n2 = 1.0 / n2;
+  c.d = d;
+  c.kind = kind;
+}
+
+// ------------------------------------------------------------------ launches
+template <typename T>
+scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* density,
+                                hipStream_t st, bool ignore_done, hipEvent_t* ev) {
+  constexpr int EMAX = (sizeof(T) == 4 ? kElemsF32 : kElemsF64) / kNT;
+  const int d = p->d;
+  const size_t esz = sizeof(cx<T>);
+  auto rec = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], st);
+  };
+  {
+    XArgs a{};
+    a.X = p->X;
+    a.Eprev = p->Ep;
+    a.Sslot = p->S;
+    a.Tslot = p->T;
+    a.phase = phase;
+    a.density = density;
+    a.part = p->part;
+    a.ctl = p->ctl;
+    a.coef = p->coef;
+    a.tw = p->tw[0];
+    a.fd = p->fd[0];
+    a.M = p->M;
+    a.n0 = p->n[0];
+    a.nlines = p->xlines;
+    a.lines_per_block = p->xL;
+    a.d = d;
+    a.invM = 1.0 / (double)p->M;
+    a.ignore_done = ignore_done;
+    // the x pass reuses its LDS for a 5 x (kNT/64) fp64 reduction
+    const size_t lds = std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
+    rec(0);
+    hipLaunchKernelGGL((xpass_kernel<T, kNT, EMAX>), dim3(p->xblocks, d, p->nsolve), dim3(kNT),
+                       lds, st, a);
+    rec(1);
+  }
+  {
+    FArgs f{};
+    f.part = p->part;
+    f.ctl = p->ctl;
+    f.hist_r = p->hist_r;
+    f.hist_s = p->hist_s;
+    f.hist_cap = p->hist_cap;
+    f.nblocks = p->xblocks;
+    f.invM = 1.0 / (double)p->M;
+    f.ignore_done = ignore_done;
+    rec(2);
+    hipLaunchKernelGGL(finalize_kernel, dim3(p->nsolve), dim3(256), 0, st, f);
+    rec(3);
+  }
+  GArgs g{};
+  g.X = p->X;
+  g.ctl = p->ctl;
+  g.coef = p->coef;
+  g.M = p->M;
+  g.n[0] = p->n[0];
+  g.n[1] = p->n[1];
+  g.n[2] = p->n[2];
+  g.d = d;
+  g.symbol = p->symbol;
+  g.ignore_done = ignore_done;
+  for (int a = 0; a < d; ++a) g.symtab[a] = p->sym[a];
+  if (d == 3) {
+    GArgs y = g;
+    y.tw = p->tw[1];
+    y.fd = p->fd[1];
+    y.C = p->yC;
+    y.stride = p->n[0];
+    y.mode = 1;
+    const size_t lds = (size_t)p->n[1] * p->yC * esz;
+    rec(4);
+    hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>),
+                       dim3((p->n[0] + p->yC - 1) / p->yC, p->n[2], p->nsolve * d), dim3(kNT), lds,
+                       st, y);
+    rec(5);
+  }
+  {
+    GArgs q = g;
+    const int nl = p->n[d - 1];
+    q.tw = p->tw[d - 1];
+    q.fd = p->fd[d - 1];
+    q.C = p->gC;
+    q.stride = d == 2 ? p->n[0] : p->n[0] * p->n[1];
+    q.mode = 0;
+    const size_t lds = (size_t)nl * d * p->gC * esz;
+    rec(6);
+    hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>),
+                       dim3((p->n[0] + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve),
+                       dim3(kNT), lds, st, q);
+    rec(7);
+  }
+  if (d == 3) {
+    GArgs y = g;
+    y.tw = p->tw[1];
+    y.fd = p->fd[1];
+    y.C = p->yC;
+    y.stride = p->n[0];
+    y.mode = 2;
+    const size_t lds = (size_t)p->n[1] * p->yC * esz;
+    rec(8);
+    hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>),
+                       dim3((p->n[0] + p->yC - 1) / p->yC, p->n[2], p->nsolve * d), dim3(kNT), lds,
+                       st, y);
+    rec(9);
+  }
+  SCFFT_HIP(hipGetLastError());
+  return SCFFT_OK;
+}
+
+scfft_status launch_iteration(Plan* p, const uint8_t* phase, const double* density, hipStream_t st,
+                              bool ignore_done = false, hipEvent_t* ev = nullptr) {
+  if (p->prec == SCFFT_FP32)
+    return launch_iteration_t<float>(p, phase, density, st, ignore_done, ev);
+  return launch_iteration_t<double>(p, phase, density, st, ignore_done, ev);
+}
+
+scfft_status launch_init(Plan* p, hipStream_t st) {
+  InitArgs a{};
+  a.X = p->X;
+  a.Sslot = p->S;
+  a.Tslot = p->T;
+  a.ctl = p->ctl;
+  a.coef = p->coef;
+  a.M = p->M;
+  a.d = p->d;
+  a.n0 = p->n[0];
+  a.nsolve = p->nsolve;
+  a.has_st = p->st ? 1 : 0;
+  a.src_scale = (double)p->M;
+  const long long tot = (long long)p->nsolve * p->d * p->M;
+  const int blocks = (int)std::min<long long>((tot + 255) / 256, 65536);
+  if (p->nsolve > 256) return SCFFT_ERR_INVALID_ARG;
+  if (p->prec == SCFFT_FP32)
+    hipLaunchKernelGGL(init_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(init_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+  SCFFT_HIP(hipGetLastError());
+  return SCFFT_OK;
+}
+
+scfft_status launch_extract(Plan* p, int solve, const uint8_t* phase, const double* density,
+                            scfft_c64* E, scfft_c64* J, hipStream_t st) {
+  if (!E && !J) return SCFFT_OK;
+  ExtractArgs a{};
+  a.Eprev = p->Ep;
+  a.phase = phase;
+  a.density = density;
+  a.coef = p->coef;
+  a.E = reinterpret_cast<double*>(E);
+  a.J = reinterpret_cast<double*>(J);
+  a.M = p->M;
+  a.d = p->d;
+  a.solve = solve;
+  const long long tot = (long long)p->d * p->M;
+  const int blocks = (int)std::min<long long>((tot + 255) / 256, 65536);
+  if (p->prec == SCFFT_FP32)
+    hipLaunchKernelGGL(extract_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(extract_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+  SCFFT_HIP(hipGetLastError());
+  return SCFFT_OK;
+}
+
+// Iterate every solve of the given plans until all have stopped.
+scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const uint8_t*>& phases,
+                      const std::vector<const double*>& dens, int max_iter, int check_every,
+                      hipStream_t st, double* elapsed_ms) {
+  hipEvent_t e0, e1;
+  SCFFT_HIP(hipEventCreate(&e0));
+  SCFFT_HIP(hipEventCreate(&e1));
+  SCFFT_HIP(hipEventRecord(e0, st));
+  const int ce = std::max(1, check_every);
+  const long long max_chunks = (long long)(max_iter + 1) / ce + 3;
+  std::vector<std::vector<SolveCtl>> host(plans.size());
+  bool all_done = false;
+  scfft_status rc = SCFFT_OK;
+  for (long long chunk = 0; chunk < max_chunks && !all_done; ++chunk) {
+    for (int k = 0; k < ce; ++k)
+      for (size_t i = 0; i < plans.size(); ++i) {
+        rc = launch_iteration(plans[i], phases[i], dens[i], st);
+        if (rc != SCFFT_OK) return rc;
+      }
+    all_done = true;
+    for (size_t i = 0; i < plans.size(); ++i) {
+      host[i].resize(plans[i]->nsolve);
+      SCFFT_HIP(hipMemcpyAsync(host[i].data(), plans[i]->ctl, sizeof(SolveCtl) * plans[i]->nsolve,
+                               hipMemcpyDeviceToHost, st));
+    }
+    SCFFT_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < plans.size() && all_done; ++i)
+      for (const auto& c : host[i])
+        if (!c.done) {
+          all_done = false;
+          break;
+        }
+  }
+  SCFFT_HIP(hipEventRecord(e1, st));
+  SCFFT_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  SCFFT_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (elapsed_ms) *elapsed_ms = ms;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!all_done) return SCFFT_ERR_DEVICE;   // the device never set its stop flag
+  return SCFFT_OK;
+}
+
+scfft_status read_result(Plan* p, int solve, const scfft_problem* prob, scfft_result* res,
+                         hipStream_t st, double elapsed) {
+  SolveCtl c;
+  SCFFT_HIP(hipMemcpyAsync(&c, p->ctl + solve, sizeof(SolveCtl), hipMemcpyDeviceToHost, st));
+  scfft_status rc = launch_extract(p, solve, prob->phase, prob->density, res->E, res->J, st);
+  if (rc != SCFFT_OK) return rc;
+  const int n = c.iter;
+  if (res->history_cap > 0 && (res->residual_history || res->sigma_history)) {
+    const int cnt = std::min(std::min(res->history_cap, n + 1), p->hist_cap);
+    if (res->residual_history)
+      SCFFT_HIP(hipMemcpyAsync(res->residual_history, p->hist_r + (size_t)solve * p->hist_cap,
+                               sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+    if (res->sigma_history)
+      SCFFT_HIP(hipMemcpyAsync(res->sigma_history, p->hist_s + (size_t)solve * p->hist_cap * 2,
+                               2 * sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+  }
+  SCFFT_HIP(hipStreamSynchronize(st));
+  res->sigma_star.re = c.sstar_re;
+  res->sigma_star.im = c.sstar_im;
+  for (int i = 0; i < 3; ++i) {
+    res->mean_J[i].re = i < p->d ? c.meanJ[2 * i] : 0.0;
+    res->mean_J[i].im = i < p->d ? c.meanJ[2 * i + 1] : 0.0;
+  }
+  res->iterations = n;
+  res->residual = c.res;
+  res->status = c.status;
+  res->elapsed_ms = elapsed;
+  return (scfft_status)c.status;
+}
+
+bool bad_e0(const scfft_problem* p) {
+  double n2 = 0;
+  for (int i = 0; i < p->d; ++i) {
+    if (!std::isfinite(p->e0[i])) return true;
+    n2 += p->e0[i] * p->e0[i];
+  }
+  return !(n2 > 0);
+}
+
+// Validates a problem/options pair and builds the solve spec.
+scfft_status prepare(const scfft_problem* prob, const scfft_options* opt, cd s1, SolveSpec* sp) {
+  if (!prob || !opt) return SCFFT_ERR_INVALID_ARG;
+  scfft_status rc = check_dims(prob->d, prob->n, opt->precision);
+  if (rc != SCFFT_OK) return rc;
+  if (opt->precision != SCFFT_FP32 && opt->precision != SCFFT_FP64) return SCFFT_ERR_INVALID_ARG;
+  if (opt->symbol < 0 || opt->symbol > 2) return SCFFT_ERR_INVALID_ARG;
+  if (!prob->phase && !prob->density) return SCFFT_ERR_INVALID_ARG;
+  if (bad_e0(prob) || opt->max_iter < 0 || std::isnan(opt->tol)) return SCFFT_ERR_INVALID_ARG;
+  if (!std::isfinite(s1.real()) || !std::isfinite(s1.imag())) return SCFFT_ERR_INVALID_ARG;
+  const bool acc = opt->scheme == SCFFT_ACC_EM || opt->scheme == SCFFT_ACC_MS;
+  if (acc && prob->density) return SCFFT_ERR_INVALID_ARG;
+  Scalars sc{};
+  rc = scheme_scalars(opt->scheme, s1, opt->alpha, opt->beta, &sc);
+  if (rc != SCFFT_OK) return rc;
+  sp->s1 = s1;
+  sp->sc = sc;
+  sp->power_phase = 1;
+  if (opt->scheme == SCFFT_MS) sp->kind = K_MS;
+  else if (opt->scheme == SCFFT_EM) sp->kind = K_EM;
+  else if (opt->scheme == SCFFT_ACC_EM) sp->kind = K_ACC_EM;
+  else sp->kind = K_ACC_MS;
+  sp->s0 = sc.sigma0;
+  if (!acc && opt->sigma0_set) sp->s0 = cd(opt->sigma0.re, opt->sigma0.im);
+  if (std::abs(sp->s0) == 0.0) return SCFFT_ERR_INVALID_ARG;
+  return SCFFT_OK;
+}
+
+// Reference conductivity of a graded medium from its extreme conductivities
+// (the device computes the extremes; sigma is 1 + (sigma1-1) rho, rho in [0,1]).
+cd graded_sigma0(int scheme, cd s1) {
+  // sigma ranges over the segment [1, sigma1]
+  if (scheme == SCFFT_MS) return (s1 + 1.0) / 2.0;
+  return std::sqrt(s1);
+}
+
+}  // namespace
+}  // namespace scfft
+
+using namespace scfft;
+
+extern "C" {
+
+void scfft_default_options(scfft_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->scheme = SCFFT_ACC_EM;
+  o->precision = SCFFT_FP64;
+  o->symbol = SCFFT_GAMMA_ROTATED;
+  o->alpha = 0.25;
+  o->beta = 4.0;
+  o->tol = 1e-8;
+  o->max_iter = 1000;
+  o->check_every = 16;
+  o->stag_window = 20;
+  o->div_factor = 1e3;
+  o->stream = nullptr;
+}
+
+const char* scfft_status_string(int s) {
+  switch (s) {
+    case SCFFT_OK: return "ok";
+    case SCFFT_ERR_INVALID_ARG: return "invalid argument";
+    case SCFFT_ERR_SLIT: return "sigma1 lies on the scheme's slit";
+    case SCFFT_ERR_NOT_CONVERGED: return "not converged within max_iter";
+    case SCFFT_ERR_DIVERGED: return "diverged";
+    case SCFFT_ERR_STAGNATED: return "stagnated";
+    case SCFFT_ERR_DEVICE: return "HIP device error";
+    case SCFFT_ERR_OOM: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+const char* scfft_version(void) { return "scfft 0.1 (gfx950)"; }
+
+void scfft_release(void) {
+  std::lock_guard<std::mutex> lk(g_mutex);
+  for (auto& kv : g_plans) free_plan(kv.second);
+  g_plans.clear();
+}
+
+scfft_status scfft_scheme_scalars(int scheme, scfft_c64 sigma1, double alpha, double beta,
+                                  scfft_c64* out) {
+  if (!out) return SCFFT_ERR_INVALID_ARG;
+  Scalars sc{};
+  scfft_status rc = scheme_scalars(scheme, cd(sigma1.re, sigma1.im), alpha, beta, &sc);
+  if (rc != SCFFT_OK) return rc;
+  const cd v[8] = {sc.sigma0, sc.t, sc.z, sc.p[0], sc.p[1], sc.p[2], sc.e2p, sc.j3p};
+  for (int i = 0; i < 8; ++i) {
+    out[i].re = v[i].real();
+    out[i].im = v[i].imag();
+  }
+  return SCFFT_OK;
+}
+
+scfft_c64 scfft_sigma1_from_z(double a, double b, scfft_c64 zz) {
+  const cd z(zz.re, zz.im);
+  const cd w = (1.0 + z) / (1.0 - z);
+  const cd t = w * w;
+  // t (s + b)(1 + a) = (s + a)(1 + b), solved for s
+  const cd s = (a * (1.0 + b) - t * b * (1.0 + a)) / (t * (1.0 + a) - (1.0 + b));
+  return scfft_c64{s.real(), s.imag()};
+}
+
+scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, scfft_result* res) {
+  if (!res) return SCFFT_ERR_INVALID_ARG;
+  SolveSpec sp{};
+  if (!prob) return SCFFT_ERR_INVALID_ARG;
+  scfft_status rc = prepare(prob, opt, cd(prob->sigma1.re, prob->sigma1.im), &sp);
+  if (rc != SCFFT_OK) {
+    res->status = rc;
+    return rc;
+  }
+  if (prob->density && !opt->sigma0_set) sp.s0 = graded_sigma0(opt->scheme, sp.s1);
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
+  Plan* p = nullptr;
+  const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, opt->max_iter + 1);
+  if (rc != SCFFT_OK) return rc;
+  SolveCtl c;
+  SolveCoef cf;
+  fill_ctl(c, *opt, sp.kind, prob->d, prob->e0);
+  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
+  SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  rc = launch_init(p, st);
+  if (rc != SCFFT_OK) return rc;
+  double ms = 0;
+  rc = run_loop({p}, {prob->phase}, {prob->density}, opt->max_iter, opt->check_every, st, &ms);
+  if (rc != SCFFT_OK) return rc;
+  return read_result(p, 0, prob, res, st, ms);
+}
+
+scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scfft_options* opts,
+                               int nsig, const scfft_c64* sigma1s, scfft_result* results) {
+  if (nprob <= 0 || nsig <= 0 || nsig > 256 || !probs || !opts || !sigma1s || !results)
+    return SCFFT_ERR_INVALID_ARG;
+  const scfft_options& o0 = opts[0];
+  std::vector<std::vector<SolveSpec>> specs(nprob, std::vector<SolveSpec>(nsig));
+  bool any_acc = false;
+  for (int i = 0; i < nprob; ++i)
+    for (int j = 0; j < nsig; ++j) {
+      scfft_options o = opts[i];
+      o.precision = o0.precision;
+      o.symbol = o0.symbol;
+      const scfft_c64 s = sigma1s[(size_t)i * nsig + j];
+      scfft_status rc = prepare(&probs[i], &o, cd(s.re, s.im), &specs[i][j]);
+      if (rc != SCFFT_OK) {
+        results[(size_t)i * nsig + j].status = rc;
+        return rc;
+      }
+      if (probs[i].density && !o.sigma0_set) specs[i][j].s0 = graded_sigma0(o.scheme, specs[i][j].s1);
+      any_acc |= specs[i][j].kind == K_ACC_EM || specs[i][j].kind == K_ACC_MS;
+    }
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(o0.stream);
+  std::vector<Plan*> plans(nprob);
+  std::vector<const uint8_t*> ph(nprob);
+  std::vector<const double*> de(nprob);
+  for (int i = 0; i < nprob; ++i) {
+    scfft_status rc = get_plan(probs[i].d, probs[i].n, o0.precision, nsig, any_acc, o0.symbol, st,
+                               &plans[i], i);
+    if (rc != SCFFT_OK) return rc;
+    rc = ensure_hist(plans[i], o0.max_iter + 1);
+    if (rc != SCFFT_OK) return rc;
+    std::vector<SolveCtl> c(nsig);
+    std::vector<SolveCoef> cf(nsig);
+    for (int j = 0; j < nsig; ++j) {
+      fill_ctl(c[j], o0, specs[i][j].kind, probs[i].d, probs[i].e0);
+      fill_coef(cf[j], specs[i][j], probs[i].density != nullptr, probs[i].d, probs[i].e0,
+                (double)plans[i]->M);
+    }
+    SCFFT_HIP(hipMemcpyAsync(plans[i]->ctl, c.data(), sizeof(SolveCtl) * nsig,
+                             hipMemcpyHostToDevice, st));
+    SCFFT_HIP(hipMemcpyAsync(plans[i]->coef, cf.data(), sizeof(SolveCoef) * nsig,
+                             hipMemcpyHostToDevice, st));
+    SCFFT_HIP(hipStreamSynchronize(st));
+    rc = launch_init(plans[i], st);
+    if (rc != SCFFT_OK) return rc;
+    ph[i] = probs[i].phase;
+    de[i] = probs[i].density;
+  }
+  double ms = 0;
+  scfft_status rc = run_loop(plans, ph, de, o0.max_iter, o0.check_every, st, &ms);
+  if (rc != SCFFT_OK) return rc;
+  scfft_status worst = SCFFT_OK;
+  for (int i = 0; i < nprob; ++i)
+    for (int j = 0; j < nsig; ++j) {
+      scfft_result* r = &results[(size_t)i * nsig + j];
+      scfft_status s = read_result(plans[i], j, &probs[i], r, st, ms);
+      if (s == SCFFT_ERR_DEVICE || s == SCFFT_ERR_OOM) return s;
+      if (s < worst) worst = s;
+    }
+  return worst;
+}
+
+scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int symbol,
+                                     void* stream, double* alpha, double* beta, double* mu_min,
+                                     double* mu_max) {
+  if (!prob || !prob->phase || iters < 0 || symbol < 0 || symbol > 2) return SCFFT_ERR_INVALID_ARG;
+  scfft_status rc = check_dims(prob->d, prob->n, SCFFT_FP64);
+  if (rc != SCFFT_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Plan* p = nullptr;
+  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 2, false, symbol, st, &p);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, iters + 2);
+  if (rc != SCFFT_OK) return rc;
+  scfft_options o;
+  scfft_default_options(&o);
+  o.tol = -1.0;
+  o.max_iter = iters + 1;
+  o.stag_window = 0;
+  o.div_factor = 0.0;
+  const double e0[3] = {1.0, 0.0, 0.0};
+  SolveCtl c[2];
+  SolveCoef cf[2];
+  for (int k = 0; k < 2; ++k) {
+    SolveSpec sp{};
+    sp.kind = K_POWER;
+    sp.power_phase = k == 0 ? 1 : 0;
+    fill_ctl(c[k], o, K_POWER, prob->d, e0);
+    fill_coef(cf[k], sp, false, prob->d, e0, (double)p->M);
+  }
+  SCFFT_HIP(hipMemcpyAsync(p->ctl, c, sizeof(c), hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p->coef, cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  rc = launch_init(p, st);
+  if (rc != SCFFT_OK) return rc;
+  double ms = 0;
+  rc = run_loop({p}, {prob->phase}, {nullptr}, o.max_iter, 32, st, &ms);
+  if (rc != SCFFT_OK) return rc;
+  SolveCtl h[2];
+  SCFFT_HIP(hipMemcpyAsync(h, p->ctl, sizeof(h), hipMemcpyDeviceToHost, st));
+  SCFFT_HIP(hipStreamSynchronize(st));
+  const double mmax = h[0].lam;
+  const double mmin = 1.0 - h[1].lam;
+  if (mu_max) *mu_max = mmax;
+  if (mu_min) *mu_min = mmin;
+  if (alpha) *alpha = 1.0 / mmax - 1.0;
+  if (beta) *beta = 1.0 / mmin - 1.0;
+  return SCFFT_OK;
+}
+
+scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt, scfft_c64* g,
+                            scfft_c64* drho, scfft_c64* dsigma1, scfft_result* fwd,
+                            scfft_result* adj) {
+  if (!prob || !opt) return SCFFT_ERR_INVALID_ARG;
+  if (opt->symbol == SCFFT_GAMMA_NETWORK) return SCFFT_ERR_INVALID_ARG;
+  scfft_options o = *opt;
+  o.scheme = SCFFT_EM;
+  const cd s1(prob->sigma1.re, prob->sigma1.im);
+  SolveSpec sp{};
+  scfft_status rc = prepare(prob, &o, s1, &sp);
+  if (rc != SCFFT_OK) return rc;
+  if (!o.sigma0_set) sp.s0 = std::sqrt(s1);   // sqrt(sigma_min sigma_max) with sigma in [1, sigma1]
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
+  double* Ef = nullptr;
+  double* part = nullptr;
+  double* sum = nullptr;
+  const long long M = (long long)prob->n[0] * prob->n[1] * (prob->d == 3 ? prob->n[2] : 1);
+  const int gblocks = (int)std::min<long long>((M + 255) / 256, 4096);
+  SCFFT_HIP(hipMalloc(&Ef, sizeof(double) * 2 * prob->d * M));
+  if (hipMalloc(&part, sizeof(double) * 2 * gblocks) != hipSuccess ||
+      hipMalloc(&sum, sizeof(double) * 2) != hipSuccess) {
+    (void)hipFree(Ef);
+    if (part) (void)hipFree(part);
+    return SCFFT_ERR_OOM;
+  }
+  scfft_result rf{};
+  scfft_result ra{};
+  if (fwd) rf = *fwd;
+  if (adj) ra = *adj;
+  rf.E = reinterpret_cast<scfft_c64*>(Ef);
+  rf.J = fwd ? fwd->J : nullptr;
+  ra.E = nullptr;
+  ra.J = nullptr;
+  scfft_status out = SCFFT_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mutex);
+    Plan* p = nullptr;
+    rc = get_plan(prob->d, prob->n, o.precision, 1, false, o.symbol, st, &p);
+    if (rc == SCFFT_OK) rc = ensure_hist(p, o.max_iter + 1);
+    for (int pass = 0; pass < 2 && rc == SCFFT_OK; ++pass) {
+      SolveSpec s = sp;
+      s.kind = pass == 0 ? K_EM : K_ADJ;
+      SolveCtl c;
+      SolveCoef cf;
+      fill_ctl(c, o, s.kind, prob->d, prob->e0);
+      fill_coef(cf, s, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
+      if (hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st) != hipSuccess) {
+        rc = SCFFT_ERR_DEVICE;
+        break;
+      }
+      rc = launch_init(p, st);
+      double ms = 0;
+      if (rc == SCFFT_OK)
+        rc = run_loop({p}, {prob->phase}, {prob->density}, o.max_iter, o.check_every, st, &ms);
+      if (rc != SCFFT_OK) break;
+      scfft_status s2 = read_result(p, 0, prob, pass == 0 ? &rf : &ra, st, ms);
+      if (s2 == SCFFT_ERR_DEVICE || s2 == SCFFT_ERR_OOM) {
+        rc = s2;
+        break;
+      }
+      if (s2 < out) out = s2;
+    }
+    if (rc == SCFFT_OK) {
+      GradArgs a{};
+      a.E = Ef;
+      a.Y = p->Ep;
+      a.phase = prob->phase;
+      a.density = prob->density;
+      a.g = reinterpret_cast<double*>(g);
+      a.drho = reinterpret_cast<double*>(drho);
+      a.part = part;
+      a.s1[0] = s1.real();
+      a.s1[1] = s1.imag();
+      a.s0[0] = sp.s0.real();
+      a.s0[1] = sp.s0.imag();
+      double n2 = 0;
+      for (int i = 0; i < prob->d; ++i) {
+        a.e0[i] = prob->e0[i];
+        n2 += prob->e0[i] * prob->e0[i];
+      }
+      a.scale = 1.0 / ((double)M * n2);
+      a.M = M;
+      a.d = prob->d;
+      if (o.precision == SCFFT_FP32)
+        hipLaunchKernelGGL(gradient_kernel<float>, dim3(gblocks), dim3(256), 0, st, a);
+      else
+        hipLaunchKernelGGL(gradient_kernel<double>, dim3(gblocks), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, part, gblocks, sum);
+      double hs[2] = {0, 0};
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(hs, sum, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        rc = SCFFT_ERR_DEVICE;
+      if (dsigma1) {
+        dsigma1->re = hs[0];
+        dsigma1->im = hs[1];
+      }
+    }
+  }
+  if (fwd) {
+    scfft_c64* keepE = fwd->E;
+    *fwd = rf;
+    fwd->E = keepE;
+    if (keepE && rc == SCFFT_OK)
+      (void)hipMemcpyAsync(keepE, Ef, sizeof(double) * 2 * prob->d * M, hipMemcpyDeviceToDevice, st);
+  }
+  if (adj) {
+    scfft_c64* kE = adj->E;
+    scfft_c64* kJ = adj->J;
+    *adj = ra;
+    adj->E = kE;
+    adj->J = kJ;
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(Ef);
+  (void)hipFree(part);
+  (void)hipFree(sum);
+  if (rc != SCFFT_OK) return rc;
+  return out;
+}
+
+scfft_status scfft_profile_passes(const scfft_problem* prob, const scfft_options* opt, int iters,
+                                  double* ms, int cap) {
+  if (!prob || !opt || !ms || cap < 5 || iters < 1) return SCFFT_ERR_INVALID_ARG;
+  SolveSpec sp{};
+  scfft_status rc = prepare(prob, opt, cd(prob->sigma1.re, prob->sigma1.im), &sp);
+  if (rc != SCFFT_OK) return rc;
+  if (prob->density && !opt->sigma0_set) sp.s0 = graded_sigma0(opt->scheme, sp.s1);
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
+  Plan* p = nullptr;
+  const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, iters + 2);
+  if (rc != SCFFT_OK) return rc;
+  scfft_options o = *opt;
+  o.tol = -1;
+  o.max_iter = iters + 1;
+  SolveCtl c;
+  SolveCoef cf;
+  fill_ctl(c, o, sp.kind, prob->d, prob->e0);
+  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
+  SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  rc = launch_init(p, st);
+  if (rc != SCFFT_OK) return rc;
+  hipEvent_t ev[10];
+  for (auto& e : ev) SCFFT_HIP(hipEventCreate(&e));
+  double acc_ms[5] = {0, 0, 0, 0, 0};
+  for (int it = 0; it < iters; ++it) {
+    rc = launch_iteration(p, prob->phase, prob->density, st, true, ev);
+    if (rc != SCFFT_OK) break;
+    SCFFT_HIP(hipEventSynchronize(ev[p->d == 3 ? 9 : 7]));
+    const int pairs[5][2] = {{0, 1}, {6, 7}, {4, 5}, {8, 9}, {2, 3}};
+    for (int k = 0; k < 5; ++k) {
+      if (p->d == 2 && (k == 2 || k == 3)) continue;
+      float t = 0;
+      SCFFT_HIP(hipEventElapsedTime(&t, ev[pairs[k][0]], ev[pairs[k][1]]));
+      acc_ms[k] += t;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  for (int k = 0; k < 5; ++k) ms[k] = acc_ms[k] / iters;
+  return rc;
+}
+
+}  // extern "C"

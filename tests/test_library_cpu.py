@@ -1,0 +1,153 @@
+"""Host-side checks of libscfft (no GPU needed).
+
+The library loads, exports every entry point include/scfft.h declares, its
+host scalar math agrees with the oracle, and argument validation rejects bad
+input before touching the device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import scalars
+from paper_2001_08289_amd import scfft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "scfft.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(scfft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert "scfft_solve" in names and len(names) >= 10
+    lib = ctypes.CDLL(scfft._LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(scfft.EXPORTS) == set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The binding's ctypes mirrors have the C layout the header defines (gcc)."""
+    import subprocess
+    structs = {"scfft_problem": scfft.Problem, "scfft_options": scfft.Options,
+               "scfft_result": scfft.Result, "scfft_c64": scfft.c64}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "scfft.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    for line in out.splitlines():
+        cname, field, val = line.split()
+        py = structs[cname]
+        if field == "size":
+            assert ctypes.sizeof(py) == int(val), cname
+        else:
+            assert getattr(py, field).offset == int(val), (cname, field)
+
+
+@pytest.mark.parametrize("ab", [(0.25, 4.0), (1 / 3, 3.0), (0.0625, 16.0)])
+@pytest.mark.parametrize("s1", [10.0, 100.0, 0.01, 3 + 2j, -0.1 + 0.5j, 0.0])
+def test_scheme_scalars_match_oracle(ab, s1):
+    a, b = ab
+    got = scfft.scheme_scalars("acc_em", s1, a, b)
+    t = scalars.t_map(s1, a, b)
+    assert abs(got["t"] - t) < 1e-13 * max(1, abs(t))
+    assert abs(got["z"] - scalars.z_sqrt(t)) < 1e-13
+    p = scalars.p_from_interval(a, b)
+    assert np.allclose(got["p"], p, rtol=1e-14)
+    assert abs(got["e2p"] - scalars.e2_prime(t, p)) < 1e-12 * max(1, abs(got["e2p"]))
+    assert abs(got["j3p"] - scalars.j3_prime(t, p)) < 1e-12 * max(1, abs(got["j3p"]))
+    ms = scfft.scheme_scalars("acc_ms", s1, a, b)
+    assert abs(ms["z"] - (t - 1) / (t + 1)) < 1e-13
+    if s1 != 0.0:
+        em = scfft.scheme_scalars("em", s1)
+        assert abs(em["z"] - scalars.z_sqrt(s1)) < 1e-14
+    assert abs(scfft.scheme_scalars("ms", s1)["z"] - scalars.z_ms(s1)) < 1e-14
+
+
+def test_sigma1_from_z_matches_oracle():
+    for z in (0.3 + 0.2j, -0.5j, 0.59 * np.exp(2.1j)):
+        got = scfft.sigma1_from_z(0.0625, 16.0, z)
+        assert abs(got - scalars.sigma1_from_z(z, 0.0625, 16.0)) < 1e-12 * abs(got)
+
+
+def test_slit_and_interval_rejected():
+    with pytest.raises(scfft.ScfftError) as e:
+        scfft.scheme_scalars("acc_em", -1.0, 0.25, 4.0)
+    assert e.value.status == scfft.ERR_SLIT
+    with pytest.raises(scfft.ScfftError) as e:
+        scfft.scheme_scalars("em", -2.0)
+    assert e.value.status == scfft.ERR_SLIT
+    with pytest.raises(scfft.ScfftError) as e:
+        scfft.scheme_scalars("acc_em", 1.0, 4.0, 0.25)
+    assert e.value.status == scfft.ERR_INVALID_ARG
+
+
+def _host_problem(d=2, n=(16, 16, 1), sigma1=10.0):
+    p = scfft.Problem()
+    p.d = d
+    for i in range(3):
+        p.n[i] = n[i]
+    p.phase = 0x1000          # never dereferenced: validation fails first
+    p.sigma1 = scfft.c64.of(sigma1)
+    p.e0[0] = 1.0
+    return p
+
+
+def _host_options(**kw):
+    o = scfft.Options()
+    scfft._lib.scfft_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+@pytest.mark.parametrize("case", [
+    dict(problem=dict(d=4)),
+    dict(problem=dict(n=(14, 16, 1))),            # 7 is not a radix
+    dict(problem=dict(n=(8192, 16, 1))),          # too long
+    dict(problem=dict(n=(1, 16, 1))),
+    dict(options=dict(precision=7)),
+    dict(options=dict(symbol=5)),
+    dict(options=dict(scheme=9)),
+    dict(options=dict(max_iter=-1)),
+    dict(options=dict(alpha=0.0)),
+    dict(options=dict(alpha=2.0, beta=1.0)),
+])
+def test_invalid_arguments_rejected_on_host(case):
+    p = _host_problem(**case.get("problem", {}))
+    o = _host_options(**case.get("options", {}))
+    r = scfft.Result()
+    rc = scfft._lib.scfft_solve(ctypes.byref(p), ctypes.byref(o), ctypes.byref(r))
+    assert rc == scfft.ERR_INVALID_ARG
+
+
+def test_zero_field_and_slit_on_host():
+    p = _host_problem()
+    p.e0[0] = 0.0
+    o = _host_options()
+    r = scfft.Result()
+    assert scfft._lib.scfft_solve(ctypes.byref(p), ctypes.byref(o), ctypes.byref(r)) == scfft.ERR_INVALID_ARG
+    p = _host_problem(sigma1=-2.0)
+    assert scfft._lib.scfft_solve(ctypes.byref(p), ctypes.byref(o), ctypes.byref(r)) == scfft.ERR_SLIT
+    o = _host_options(scheme=scfft.EM)
+    p = _host_problem(sigma1=-0.5)
+    assert scfft._lib.scfft_solve(ctypes.byref(p), ctypes.byref(o), ctypes.byref(r)) == scfft.ERR_SLIT
+
+
+def test_status_strings():
+    for s in range(-7, 1):
+        assert scfft.status_string(s) and scfft.status_string(s) != "unknown status"
+    assert scfft.status_string(42) == "unknown status"

@@ -52,6 +52,114 @@ def algorithmic_bytes(scheme: str, precision: str, d: int, frac1: float):
     return {"xpass": xp, "gamma": gp, "y": gp if d == 3 else 0.0}
 
 
+def _row(r, **kw):
+    d = {"status": r["status"], "iterations": r["iterations"], "time_ms": round(r["elapsed_ms"], 3),
+         "sigma_star": complex(r["sigma_star"]).real}
+    d.update(kw)
+    return d
+
+
+def extra_configs(scfft, inputs, torch) -> dict:
+    """3D cube array, mixed-grid batched contour sweep, adjoint gradients."""
+    out = {}
+    log = lambda *a: print("#", *a, file=sys.stderr, flush=True)   # noqa: E731
+
+    # 3D cubic array of cubes at ~25% on 256^3, sigma1 = 100, interval by power iteration
+    n3 = 256
+    chi3 = torch.as_tensor(inputs.cube_array(n3)).cuda()
+    t0 = time.perf_counter()
+    est = scfft.estimate_interval(chi3, 100)
+    t_est = time.perf_counter() - t0
+    a_u = min(est["alpha"], 1.0 / est["beta"])        # alpha*beta = 1 (stability reading)
+    b_u = 1.0 / a_u
+    rows = []
+    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-8)):
+        for scheme in SCHEMES:
+            r = scfft.solve(chi3, 100.0, (1.0, 0.0, 0.0), scheme, precision=prec, alpha=a_u,
+                            beta=b_u, tol=tol, max_iter=2000, check_every=8, fields=False,
+                            history=False, raise_on_error=False)
+            rows.append(_row(r, precision=prec, scheme=scheme, tol=tol,
+                             voxel_iters_per_s=n3 ** 3 * r["iterations"] / (r["elapsed_ms"] * 1e-3)
+                             if r["elapsed_ms"] > 0 else None))
+            log("3d", rows[-1])
+    out["cube_256"] = {"interval_raw": est, "interval_used": [a_u, b_u],
+                       "estimate_s": round(t_est, 3), "runs": rows,
+                       "workload": "3D cubic array of cubes (side 161 of 256, f = 0.24875), "
+                                   "sigma1 = 100, e0 = e1"}
+    del chi3
+    scfft.release()
+
+    # batched sweep: 16 disk microstructures on mixed grids x 128 contour conductivities
+    grids = inputs.BATCH_GRIDS
+    chis, alphas, betas, sig = [], [], [], []
+    t_est = 0.0
+    for seed, n in enumerate(grids):
+        chi_np, _ = inputs.random_disks(n, seed=seed)
+        chi = torch.as_tensor(chi_np).cuda()
+        t0 = time.perf_counter()
+        e = scfft.estimate_interval(chi, 100)
+        t_est += time.perf_counter() - t0
+        a_u = min(0.8 * e["alpha"], 0.8 / e["beta"], 0.0625)
+        b_u = 1.0 / a_u
+        z = inputs.contour_points(128, 0.6)
+        chis.append(chi)
+        alphas.append(a_u)
+        betas.append(b_u)
+        sig.append([scfft.sigma1_from_z(a_u, b_u, zz) for zz in z])
+    scfft.release()
+    vox = sum(n * n for n in grids) * 128
+    res = {}
+    for prec, tol in (("fp32", 1e-6),):
+        t0 = time.perf_counter()
+        rs = scfft.solve_batch(chis, np.array(sig), scheme="acc_em", alphas=alphas, betas=betas,
+                               precision=prec, tol=tol, max_iter=400, check_every=8)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        its = np.array([r["iterations"] for r in rs])
+        stats = np.array([r["status"] for r in rs])
+        # every solve is iterated until the slowest of the batch stops; the
+        # voxel-iterations counted here are the useful ones (up to each stop)
+        useful = sum(n * n * int(its[i * 128:(i + 1) * 128].sum()) for i, n in enumerate(grids))
+        res[prec] = {"wall_s": round(wall, 3), "useful_voxel_iters_per_s": useful / wall,
+                     "iterations_min_mean_max": [int(its.min()), float(its.mean()), int(its.max())],
+                     "converged": int((stats == 0).sum()), "flagged": int((stats != 0).sum())}
+        log("batch", prec, res[prec])
+        scfft.release()
+    out["disk_batch"] = {"solves": len(rs), "voxels_per_batch_iteration": vox,
+                         "interval_estimate_s": round(t_est, 3), "runs": res,
+                         "workload": "16 periodic random-disk microstructures (seeds 0-15, radii "
+                                     "U[0.03,0.08], f >= 0.30) on grids 256..1024 x 128 sigma1 on "
+                                     "the |z''| = 0.6 contour, accelerated scheme, one batch"}
+    del chis
+
+    # adjoint gradients on a 1024^2 graded medium
+    n5 = 1024
+    rho = torch.as_tensor(inputs.density_field(n5, seed=5)).cuda()
+    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-10)):
+        t0 = time.perf_counter()
+        g = scfft.gradient(density=rho, sigma1=20.0, e0=(1.0, 0.0), precision=prec, tol=tol,
+                           max_iter=3000)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out.setdefault("gradient_1024", {})[prec] = {
+            "wall_s": round(wall, 3), "sigma_star": g["forward"]["sigma_star"].real,
+            "dsigma_dsigma1": g["dsigma1"].real,
+            "forward_iterations": g["forward"]["iterations"],
+            "adjoint_iterations": g["adjoint"]["iterations"]}
+        log("grad", prec, out["gradient_1024"][prec])
+    h = 1e-3 * 20.0
+    fp = scfft.solve(density=rho, sigma1=20.0 + h, e0=(1.0, 0.0), scheme="em", sigma0=np.sqrt(20.0),
+                     tol=1e-12, max_iter=3000, fields=False, history=False)["sigma_star"].real
+    fm = scfft.solve(density=rho, sigma1=20.0 - h, e0=(1.0, 0.0), scheme="em", sigma0=np.sqrt(20.0),
+                     tol=1e-12, max_iter=3000, fields=False, history=False)["sigma_star"].real
+    out["gradient_1024"]["central_fd_dsigma1_fp64"] = (fp - fm) / (2 * h)
+    out["gradient_1024"]["workload"] = ("sigma = 1 + 19 rho(x), rho: seeded Gaussian-filtered noise "
+                                        "(0.05 cell) clipped to [0,1], 1024^2, Eyre-Milton forward, "
+                                        "transposed Eyre-Milton adjoint")
+    scfft.release()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +168,10 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-iters", type=int, default=20)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only run the headline iteration with per-kernel timing (for rocprofv3)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 3D cube, batched-sweep and gradient workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -81,8 +193,14 @@ def main() -> int:
     e0 = (1.0, 0.0)
     exact = {s: complex(np.sqrt((1 + 3 * s) / (3 + s))) for s in SIGMAS}   # eq. J47a
 
-    # ---------------------------------------------------------- headline
     hs = HEADLINE
+    if args.profile_only:
+        prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
+                                    alpha=0.25, beta=4.0, iters=args.profile_iters)
+        print(json.dumps({"profile": prof, "config": hs, "grid": [N, N]}), flush=True)
+        return 0
+
+    # ---------------------------------------------------------- headline
     common = dict(alpha=0.25, beta=4.0, tol=-1.0, stag_window=0, div_factor=0.0,
                   check_every=64, fields=False, history=False)
     scfft.solve(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
@@ -155,6 +273,8 @@ def main() -> int:
                "sample": f"one iteration of the fp64 numpy oracle ({hs['scheme']}, 2048^2, own FFT), "
                          f"{dt:.1f} s"}
 
+    extra = {} if args.no_extra else extra_configs(scfft, inputs, torch)
+
     out = {
         "metric": "voxel-iters/s + time to 1e-8 residual, accelerated vs basic, FP32 vs FP64",
         "value": value, "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
@@ -170,6 +290,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "speedup_time_to_tol": accel,
         "sweep": sweep,
+        "extra_configs": extra,
     }
     print(json.dumps(out), flush=True)
     return 0

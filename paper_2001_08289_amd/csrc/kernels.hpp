@@ -72,6 +72,7 @@ struct XArgs {
   const void* tw;       // twiddles for n0
   FftDesc fd;
   long long M;          // voxels per field
+  long long Mh;         // stored elements of one component of X (real mode: (n0/2+1) n1 n2)
   int n0, nlines, lines_per_block, d;
   double invM;
   int ignore_done;
@@ -93,6 +94,146 @@ struct GArgs {
 
 template <typename T>
 __device__ __forceinline__ cx<T> ld2(const double* p) { return mk<T>((T)p[0], (T)p[1]); }
+
+// ------------------------------------------------------- local real-space map
+struct Acc {
+  double Jr = 0, Ji = 0, e2 = 0, d2 = 0, eJ = 0;
+};
+
+// The scheme's pointwise step at one voxel: from the scaled iterate x it
+// forms the physical field E (the Q-slot of E'' in H''), the current J, the
+// fp64 reduction terms (sum J, |E|^2, |E - E_prev|^2, Re conj(E) J), stores E
+// as the new E_prev, updates the S/T slots (H''), and returns the value the
+// forward FFT receives: MS tau = (1 - sigma/sigma0) E; EM R = Z P; H'' the
+// Q-slot of Z'' P'' (eq. J36 form) or of (I - sigma''/sigma0'') E''; the
+// power and adjoint kinds their own linear maps.
+enum MapKind { MAP_LIN = 0, MAP_LIN_DENS = 1, MAP_ACC_EM = 2, MAP_ACC_MS = 3, MAP_ANY = 4 };
+
+// MK fixes the branch at compile time (MAP_ANY decides at run time).
+template <typename T, int MK = MAP_ANY>
+struct LocalMap {
+  int kind, density, iter;
+  cx<T> cE[2], cO[2], cJ[2], cS[2];
+  cx<T> s1, s0, p1, p2, p3, z, inv1w, p1kap;
+  T invM, e0c;
+  const uint8_t* phase;
+  const double* dens;
+  cx<T>* S;
+  cx<T>* Tt;
+  cx<T>* Ep;
+
+  __device__ __forceinline__ void load(const XArgs& a, int solve, int comp, long long fbase) {
+    const SolveCoef& cf = a.coef[solve];
+    const SolveCtl& ctl = a.ctl[solve];
+    kind = cf.kind;
+    density = cf.density;
+    iter = ctl.iter;
+    for (int ph = 0; ph < 2; ++ph) {
+      cE[ph] = ld2<T>(cf.cE[ph]);
+      cO[ph] = ld2<T>(cf.cO[ph]);
+      cJ[ph] = ld2<T>(cf.cJ[ph]);
+      cS[ph] = ld2<T>(cf.cS[ph]);
+    }
+    s1 = ld2<T>(cf.s1);
+    s0 = ld2<T>(cf.s0);
+    p1 = ld2<T>(cf.p[0]);
+    p2 = ld2<T>(cf.p[1]);
+    p3 = ld2<T>(cf.p[2]);
+    z = ld2<T>(cf.z);
+    inv1w = ld2<T>(cf.inv1w);
+    p1kap = ld2<T>(cf.p1kap);
+    invM = (T)a.invM;
+    e0c = (T)ctl.e0[comp];
+    phase = a.phase;
+    dens = a.density;
+    S = a.Sslot ? reinterpret_cast<cx<T>*>(a.Sslot) + fbase : nullptr;
+    Tt = a.Tslot ? reinterpret_cast<cx<T>*>(a.Tslot) + fbase : nullptr;
+    Ep = reinterpret_cast<cx<T>*>(a.Eprev) + fbase;
+  }
+
+  __device__ __forceinline__ cx<T> apply(cx<T> raw, long long g, Acc& acc) const {
+    const cx<T> x = invM * raw;
+    cx<T> E, J, out;
+    const bool acc_kind = MK == MAP_ANY ? (kind == K_ACC_EM || kind == K_ACC_MS)
+                                        : (MK == MAP_ACC_EM || MK == MAP_ACC_MS);
+    const bool acc_em = MK == MAP_ANY ? kind == K_ACC_EM : MK == MAP_ACC_EM;
+    const bool dens_kind = MK == MAP_ANY ? density != 0 : MK == MAP_LIN_DENS;
+    if (acc_kind) {
+      const T two = (T)2;
+      const int ph = phase[g];
+      if (acc_em) {
+        if (ph) {
+          // phase 1 of H'': s = p^T (Q, S, T); Z'' = z (2 p p^T - I)
+          const cx<T> sv = S[g], tv = Tt[g];
+          const cx<T> s = p1 * x + p2 * sv + p3 * tv;
+          E = inv1w * x + p1kap * s;
+          J = s1 * E;
+          out = z * (two * (p1 * s) - x);
+          S[g] = mk<T>(0, 0) - z * (two * (p2 * s) - sv);   // W'' flips S (eq. J44)
+          Tt[g] = z * (two * (p3 * s) - tv);
+        } else {
+          E = inv1w * x;
+          J = E;
+          out = mk<T>(0, 0) - z * x;
+        }
+      } else {
+        E = x;
+        if (ph) {
+          const cx<T> sv = S[g];
+          const cx<T> s = p1 * x + p2 * sv;      // the T-slot of E'' is zero
+          J = s1 * E;
+          out = z * (x - two * (p1 * s));
+          S[g] = z * (sv - two * (p2 * s));
+        } else {
+          J = E;
+          out = z * x;
+        }
+      }
+    } else {
+      cx<T> ce, co, cj, cs;
+      if (dens_kind) {
+        // graded medium: sigma(x) = 1 + (sigma1 - 1) rho(x)
+        const T rho = (T)dens[g];
+        const cx<T> sig = mk<T>((T)1 + (s1.x - (T)1) * rho, s1.y * rho);
+        const cx<T> one = mk<T>(1, 0);
+        if (kind == K_MS) {
+          ce = one;
+          co = one - cdiv(sig, s0);
+          cj = sig;
+          cs = mk<T>(0, 0);
+        } else {
+          const cx<T> inv = cdiv(one, sig + s0);
+          co = (sig - s0) * inv;
+          if (kind == K_EM) {
+            ce = inv;
+            cj = sig;
+            cs = mk<T>(0, 0);
+          } else {  // K_ADJ
+            ce = one;
+            cj = mk<T>(0, 0);
+            cs = sig * inv;
+          }
+        }
+      } else {
+        const bool ph = phase[g] != 0;
+        ce = ph ? cE[1] : cE[0];
+        co = ph ? cO[1] : cO[0];
+        cj = ph ? cJ[1] : cJ[0];
+        cs = ph ? cS[1] : cS[0];
+      }
+      E = ce * x;
+      J = cj * E;
+      out = co * x + e0c * cs;
+    }
+    acc.Jr += (double)J.x;
+    acc.Ji += (double)J.y;
+    acc.e2 += (double)norm2(E);
+    acc.eJ += (double)(E.x * J.x + E.y * J.y);
+    if (iter >= 1) acc.d2 += (double)norm2(E - Ep[g]);
+    Ep[g] = E;
+    return out;
+  }
+};
 
 // ------------------------------------------------------------------ x pass
 template <typename T, int NT, int EMAX>
@@ -119,115 +260,16 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs a) {
   __syncthreads();
   fft_lines<T, NT, EMAX>(lds, nl, a.fd, n0, 1, false, tw, (T)1, tid);
 
-  const SolveCoef& cf = a.coef[solve];
-  const int kind = cf.kind;
-  const int iter = ctl->iter;
-  const T invM = (T)a.invM;
-  const T e0c = (T)ctl->e0[comp];
-  double aJr = 0, aJi = 0, ae2 = 0, ad2 = 0, aeJ = 0;
-
-  if (kind == K_ACC_EM || kind == K_ACC_MS) {
-    cx<T>* S = reinterpret_cast<cx<T>*>(a.Sslot) + fbase;
-    cx<T>* Tt = reinterpret_cast<cx<T>*>(a.Tslot) + fbase;
-    const cx<T> p1 = ld2<T>(cf.p[0]), p2 = ld2<T>(cf.p[1]), p3 = ld2<T>(cf.p[2]);
-    const cx<T> z = ld2<T>(cf.z);
-    const cx<T> s1 = ld2<T>(cf.s1);
-    const cx<T> inv1w = ld2<T>(cf.inv1w), p1kap = ld2<T>(cf.p1kap);
-    const T two = (T)2;
-    for (int i = tid; i < cnt; i += NT) {
-      const long long g = base + i;
-      const cx<T> q = invM * lds[i];
-      const int ph = a.phase[g];
-      cx<T> E, J, out;
-      if (kind == K_ACC_EM) {
-        if (ph) {
-          // phase 1 of H'': s = p^T (Q, S, T); Z'' = z (2 p p^T - I)
-          const cx<T> sv = S[g], tv = Tt[g];
-          const cx<T> s = p1 * q + p2 * sv + p3 * tv;
-          E = inv1w * q + p1kap * s;
-          J = s1 * E;
-          out = z * (two * (p1 * s) - q);
-          S[g] = mk<T>(0, 0) - z * (two * (p2 * s) - sv);   // W'' flips S (eq. J44)
-          Tt[g] = z * (two * (p3 * s) - tv);
-        } else {
-          E = inv1w * q;
-          J = E;
-          out = mk<T>(0, 0) - z * q;
-        }
-      } else {
-        E = q;
-        if (ph) {
-          const cx<T> sv = S[g];
-          const cx<T> s = p1 * q + p2 * sv;      // the T-slot of E'' is zero
-          J = s1 * E;
-          out = z * (q - two * (p1 * s));
-          S[g] = z * (sv - two * (p2 * s));
-        } else {
-          J = E;
-          out = z * q;
-        }
-      }
-      aJr += (double)J.x;
-      aJi += (double)J.y;
-      ae2 += (double)norm2(E);
-      aeJ += (double)(E.x * J.x + E.y * J.y);
-      if (iter >= 1) ad2 += (double)norm2(E - Ep[g]);
-      Ep[g] = E;
-      lds[i] = out;
-    }
-  } else {
-    for (int i = tid; i < cnt; i += NT) {
-      const long long g = base + i;
-      const cx<T> x = invM * lds[i];
-      cx<T> cE, cO, cJ, cS;
-      if (cf.density) {
-        // graded medium: sigma(x) = 1 + (sigma1 - 1) rho(x)
-        const T rho = (T)a.density[g];
-        const cx<T> s1 = ld2<T>(cf.s1), s0 = ld2<T>(cf.s0);
-        const cx<T> sig = mk<T>((T)1 + (s1.x - (T)1) * rho, s1.y * rho);
-        const cx<T> one = mk<T>(1, 0);
-        if (kind == K_MS) {
-          cE = one;
-          cO = one - cdiv(sig, s0);
-          cJ = sig;
-          cS = mk<T>(0, 0);
-        } else {
-          const cx<T> inv = cdiv(one, sig + s0);
-          cO = (sig - s0) * inv;
-          if (kind == K_EM) {
-            cE = inv;
-            cJ = sig;
-            cS = mk<T>(0, 0);
-          } else {  // K_ADJ
-            cE = one;
-            cJ = mk<T>(0, 0);
-            cS = sig * inv;
-          }
-        }
-      } else {
-        const int ph = a.phase[g] ? 1 : 0;
-        cE = ld2<T>(cf.cE[ph]);
-        cO = ld2<T>(cf.cO[ph]);
-        cJ = ld2<T>(cf.cJ[ph]);
-        cS = ld2<T>(cf.cS[ph]);
-      }
-      const cx<T> E = cE * x;
-      const cx<T> J = cJ * E;
-      aJr += (double)J.x;
-      aJi += (double)J.y;
-      ae2 += (double)norm2(E);
-      aeJ += (double)(E.x * J.x + E.y * J.y);
-      if (iter >= 1) ad2 += (double)norm2(E - Ep[g]);
-      Ep[g] = E;
-      lds[i] = cO * x + e0c * cS;
-    }
-  }
+  LocalMap<T> lm;
+  lm.load(a, solve, comp, fbase);
+  Acc acc;
+  for (int i = tid; i < cnt; i += NT) lds[i] = lm.apply(lds[i], base + i, acc);
   __syncthreads();
   fft_lines<T, NT, EMAX>(lds, nl, a.fd, n0, 1, false, tw, (T)-1, tid);
   for (int i = tid; i < cnt; i += NT) X[base + i] = lds[i];
 
   // deterministic workgroup reduction (wave64 shuffles, then across waves)
-  double v[5] = {aJr, aJi, ae2, ad2, aeJ};
+  double v[5] = {acc.Jr, acc.Ji, acc.e2, acc.d2, acc.eJ};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     double s = v[k];
@@ -398,6 +440,8 @@ __global__ __launch_bounds__(NT) void line_pass_kernel(GArgs a) {
 // ---------------------------------------------------------------- finalize
 struct FArgs {
   const double* part;
+  double* part2;       // [solve][groups][9] second-level sums
+  unsigned int* count; // [solve] groups finished in this launch (reset by the last)
   SolveCtl* ctl;
   double* hist_r;
   double* hist_s;
@@ -407,38 +451,67 @@ struct FArgs {
   int ignore_done;
 };
 
+// Reduction and stop rules.  Grid (groups, solves): every group sums a fixed
+// slice of the x-pass partials, the last group to finish (device-scope
+// counter) adds the group sums in fixed order and applies the stop rules, so
+// the result does not depend on scheduling.
 __global__ __launch_bounds__(256) void finalize_kernel(FArgs a) {
-  const int solve = blockIdx.x;
+  const int solve = blockIdx.y;
+  const int grp = blockIdx.x;
+  const int ngrp = gridDim.x;
   SolveCtl* ctl = a.ctl + solve;
   if (!a.ignore_done && ctl->done) return;
   const int d = ctl->d;
-  __shared__ double red[256];
-  __shared__ double tot[3 * 2 + 3];
+  __shared__ double red[9][4];
+  __shared__ double tot[9];
+  __shared__ int last;
   const int tid = threadIdx.x;
-  // per-component current sums, then e2, d2, eJ over all components
-  for (int q = 0; q < 2 * d + 3; ++q) {
-    const int c = (q < 2 * d) ? q / 2 : -1;
-    const int slot = (q < 2 * d) ? (q & 1) : (q - 2 * d + 2);
-    double s = 0;
-    if (c >= 0) {
-      const double* p = a.part + ((long long)solve * d + c) * a.nblocks * 5;
-      for (int b = tid; b < a.nblocks; b += 256) s += p[b * 5 + slot];
-    } else {
-      for (int cc = 0; cc < d; ++cc) {
-        const double* p = a.part + ((long long)solve * d + cc) * a.nblocks * 5;
-        for (int b = tid; b < a.nblocks; b += 256) s += p[b * 5 + slot];
-      }
+  const int per = (a.nblocks + ngrp - 1) / ngrp;
+  const int b0 = grp * per;
+  const int b1 = min(a.nblocks, b0 + per);
+  // per-component current sums, then |E|^2, |dE|^2, Re conj(E) J
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < d; ++c) {
+    const double* p = a.part + ((long long)solve * d + c) * a.nblocks * 5;
+    for (int b = b0 + tid; b < b1; b += 256) {
+      acc[2 * c] += p[b * 5 + 0];
+      acc[2 * c + 1] += p[b * 5 + 1];
+      acc[6] += p[b * 5 + 2];
+      acc[7] += p[b * 5 + 3];
+      acc[8] += p[b * 5 + 4];
     }
-    red[tid] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) tot[q] = red[0];
-    __syncthreads();
   }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) red[q][tid >> 6] = v;
+  }
+  __syncthreads();
+  double* p2 = a.part2 + (long long)solve * 64 * 9;
+  if (tid < 9) {
+    const double v = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+    __hip_atomic_store(p2 + grp * 9 + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned int prev = atomicAdd(a.count + solve, 1u);
+    last = (prev == (unsigned int)ngrp - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (tid < 9) {
+    double v = 0;
+    for (int g = 0; g < ngrp; ++g)
+      v += __hip_atomic_load(p2 + g * 9 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tot[tid] = v;
+  }
+  __syncthreads();
   if (tid != 0) return;
+  __hip_atomic_store(a.count + solve, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const int n = ctl->iter;
   double sr = 0, si = 0;
   for (int c = 0; c < d; ++c) {
@@ -450,7 +523,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FArgs a) {
   }
   sr *= ctl->inv_e0n2;
   si *= ctl->inv_e0n2;
-  const double e2 = tot[2 * d], d2 = tot[2 * d + 1], eJ = tot[2 * d + 2];
+  const double e2 = tot[6], d2 = tot[7], eJ = tot[8];
   const double lam = eJ / e2;
   double r = __builtin_nan("");
   if (n >= 1) r = (e2 > 0) ? sqrt(d2 / e2) : __builtin_inf();
@@ -612,10 +685,11 @@ struct GradArgs {
   int d;
 };
 
-template <typename T>
+template <typename T, bool REAL>
 __global__ __launch_bounds__(256) void gradient_kernel(GradArgs a) {
   __shared__ double red[2][4];
   const cx<T>* Y = reinterpret_cast<const cx<T>*>(a.Y);
+  const T* Yr = reinterpret_cast<const T*>(a.Y);
   double accr = 0, acci = 0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < a.M;
        i += (long long)gridDim.x * blockDim.x) {
@@ -626,7 +700,7 @@ __global__ __launch_bounds__(256) void gradient_kernel(GradArgs a) {
     for (int c = 0; c < a.d; ++c) {
       const double er = a.E[2 * (c * a.M + i)], ei = a.E[2 * (c * a.M + i) + 1];
       const double pr = ar * er - ai * ei, pi = ar * ei + ai * er;    // P = (sigma+sigma0) E
-      const cx<T> y = Y[c * a.M + i];
+      const cx<T> y = REAL ? mk<T>(Yr[c * a.M + i], (T)0) : Y[c * a.M + i];
       ypr += (double)y.x * pr - (double)y.y * pi;
       ypi += (double)y.x * pi + (double)y.y * pr;
       per += pr * a.e0[c];

@@ -1,0 +1,275 @@
+// Passes for power-of-two line lengths with the register-resident FFT.
+// Same data layout and semantics as the LDS-staged passes of kernels.hpp;
+// the host picks these whenever a line length is a power of two in
+// [16, 4096].
+#pragma once
+
+#include "kernels.hpp"
+#include "reg_fft.hpp"
+
+namespace scfft {
+
+// Block reduction of the five fp64 partial sums (wave64 shuffles, then LDS).
+template <int NTH>
+__device__ __forceinline__ void block_reduce5(Acc acc, double* red_lds, double* out, int tid) {
+  double v[5] = {acc.Jr, acc.Ji, acc.e2, acc.d2, acc.eJ};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double s = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    v[k] = s;
+  }
+  constexpr int NW = NTH / 64;
+  const int lane = tid & 63, wave = tid >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red_lds[k * NW + wave] = v[k];
+  }
+  __syncthreads();
+  if (tid < 5) {
+    double s = 0;
+    for (int w = 0; w < NW; ++w) s += red_lds[tid * NW + w];
+    out[tid] = s;
+  }
+}
+
+template <int N, int R>
+struct XPassShape {
+  static constexpr int TL = N / R;
+  static constexpr int LINES = TL >= 256 ? 1 : 256 / TL;
+  static constexpr int NTH = TL * LINES;
+};
+
+// x pass: LINES rows of one component per workgroup, TL threads per row;
+// MK selects the local map at compile time.
+template <typename T, int N, int R, int MK>
+__global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_p2_kernel(XArgs a) {
+  using SH = XPassShape<N, R>;
+  constexpr int TL = SH::TL, LINES = SH::LINES, NTH = SH::NTH;
+  constexpr int LP = P2Plan<N, R>::LP;
+  const int solve = blockIdx.z;
+  const int comp = blockIdx.y;
+  if (!a.ignore_done && a.ctl[solve].done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int line = tid / TL;
+  const int j = tid - line * TL;
+  const long long row = (long long)blockIdx.x * LINES + line;
+  const bool valid = row < a.nlines;
+  const long long fbase = ((long long)solve * a.d + comp) * a.M;
+  const long long base = row * N;
+  cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + fbase + base;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  cx<T> v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) v[i] = valid ? X[j + TL * i] : mk<T>(0, 0);
+  cx<T>* slot = lds + line * LP;
+  reg_fft<T, N, R>(v, slot, j, (T)1, tw);
+  LocalMap<T, MK> lm;
+  lm.load(a, solve, comp, fbase);
+  Acc acc;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) v[i] = lm.apply(v[i], base + j + TL * i, acc);
+  }
+  reg_fft<T, N, R>(v, slot, j, (T)-1, tw);
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) X[j + TL * i] = v[i];
+  }
+  __syncthreads();   // the FFT slots are free again
+  block_reduce5<NTH>(acc, reinterpret_cast<double*>(smem_raw),
+                     a.part + (((long long)solve * a.d + comp) * gridDim.x + blockIdx.x) * 5, tid);
+}
+
+// Lines per workgroup of the strided passes: at most 16 (128-byte row
+// segments in fp32), at most 1024 threads, and the LDS slots within 64 KiB.
+template <typename T, int N, int R, bool PAD>
+struct LineShapeBase {
+  static constexpr int TL = N / R;
+  static constexpr int LP = PAD ? P2Plan<N, R>::LP : N;
+  static constexpr int c1 = 16;
+  static constexpr int c2 = 1024 / TL;
+  static constexpr int c3 = 65536 / (LP * (int)sizeof(cx<T>));
+  static constexpr int C0 = c1 < c2 ? (c1 < c3 ? c1 : c3) : (c2 < c3 ? c2 : c3);
+};
+// CW = 0 picks the default tile; CW > 0 caps the tile width (tuning).
+// The tile is the widest power of two that fits unpadded, capped at 8 lines
+// and 512 threads (the measured optimum on MI355X: 2 columns at 2048^2, 8
+// lines at 256^3); the padded slot layout is used whenever it still fits.
+template <typename T, int N, int R, int CW = 0>
+struct LineShape {
+  using B = LineShapeBase<T, N, R, false>;
+  static constexpr int TL = B::TL;
+  static constexpr int CF = B::C0 >= 8 ? 8 : B::C0 >= 4 ? 4 : B::C0 >= 2 ? 2 : 1;
+  static constexpr int CT = 512 / TL > 0 ? 512 / TL : 1;
+  static constexpr int CM = CF < CT ? CF : CT;
+  static constexpr int C = (CW > 0 && CW < CM) ? CW : CM;
+  static constexpr bool PAD = C * P2Plan<N, R>::LP * (int)sizeof(cx<T>) <= 65536;
+  static constexpr int LP = PAD ? P2Plan<N, R>::LP : N;
+  static constexpr int NTH = TL * C;
+};
+
+// Symbol vector of eq. J11 on the grid for one mode, compile-time dimension.
+template <typename T, int D>
+__device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* nv) {
+  if (a.symbol == SYM_ROTATED) {
+    T s[D], c[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double* t = a.symtab[q] + 2 * m[q];
+      s[q] = (T)t[0];
+      c[q] = (T)t[1];
+    }
+    T nrm = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      T v = s[q];
+#pragma unroll
+      for (int l = 0; l < D; ++l)
+        if (l != q) v *= c[l];
+      nv[q] = mk<T>(v, 0);
+      nrm += v * v;
+    }
+    if (nrm == (T)0) {
+      // n = 0 at m != 0 (two or more Nyquist indices): Nyquist-indicator direction
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const T v = (c[q] == (T)0) ? (T)1 : (T)0;
+        nv[q] = mk<T>(v, 0);
+        nrm += v;
+      }
+    }
+    return nrm;
+  } else if (a.symbol == SYM_SPECTRAL) {
+    T v[D];
+    bool nyq[D];
+    bool has_nyq = false, has_other = false;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double* t = a.symtab[q] + 2 * m[q];
+      v[q] = (T)t[0];
+      nyq[q] = t[1] != 0.0;
+      has_nyq |= nyq[q];
+      has_other |= (!nyq[q]) && (v[q] != (T)0);
+    }
+    T nrm = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const T w = (has_nyq && has_other && nyq[q]) ? (T)0 : v[q];
+      nv[q] = mk<T>(w, 0);
+      nrm += w * w;
+    }
+    return nrm;
+  } else {
+    T nrm = 0;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const double* t = a.symtab[q] + 2 * m[q];
+      nv[q] = mk<T>((T)t[0], (T)t[1]);
+      nrm += norm2(nv[q]);
+    }
+    return nrm;
+  }
+}
+
+// Strided passes: a tile of C lines adjacent along x, thread (j, c) with c
+// fastest so that each row of the tile is one contiguous segment.
+//   mode 0: forward FFT, Gamma_1 (eq. J11 / J44-J45) with the scheme's k = 0
+//           source, inverse FFT -- all D = d components of one solve;
+//   mode 1 / 2: forward / inverse FFT only (3D y pass), D = 1 component.
+// Tiles are ordered so that consecutive tiles run on the same XCD (the
+// hardware deals workgroups round-robin over the 8 XCDs), letting one L2
+// serve the neighbouring row segments of adjacent tiles.
+template <typename T, int N, int R, int D, int CW>
+__global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(GArgs a) {
+  using SH = LineShape<T, N, R, CW>;
+  constexpr int TL = SH::TL, C = SH::C, LP = SH::LP;
+  const bool gam = (a.mode == 0);
+  const int d = a.d;
+  const int solve = gam ? blockIdx.z : blockIdx.z / d;
+  const int comp0 = gam ? 0 : blockIdx.z % d;
+  if (!a.ignore_done && a.ctl[solve].done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int c = tid % C;
+  const int j = tid / C;
+  // XCD-aware tile order
+  const int nbx = gridDim.x, nby = gridDim.y;
+  const int nb = nbx * nby;
+  const int b = blockIdx.y * nbx + blockIdx.x;
+  int t = b;
+  const int full = nb - nb % 8;
+  if (b < full) t = (b % 8) * (full / 8) + b / 8;
+  const int bx = t % nbx, by = t / nbx;
+  const int x0 = bx * C;
+  const bool valid = x0 + c < a.n[0];
+  const long long off = x0 + c + (long long)by * a.n[0] * (gam ? 1 : a.n[1]);
+  const long long M = a.M;
+  cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M + off;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  cx<T> v[D][R];
+#pragma unroll
+  for (int cc = 0; cc < D; ++cc)
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      v[cc][i] = valid ? X[cc * M + (long long)(j + TL * i) * a.stride] : mk<T>(0, 0);
+  cx<T>* slot = lds + c * LP;
+  if (a.mode != 2) {
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) {
+      reg_fft<T, N, R, SH::PAD>(v[cc], slot, j, (T)-1, tw);
+    }
+  }
+  if (gam && valid) {
+    const SolveCoef& cf = a.coef[solve];
+    const T ga = (T)cf.ga, gb = (T)cf.gb, keep = (T)cf.kz_keep;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      int m[3];
+      m[0] = x0 + c;
+      if (D == 2) {
+        m[1] = j + TL * i;
+      } else {
+        m[1] = by;
+        m[2] = j + TL * i;
+      }
+      const bool zero = (m[0] == 0) && (m[1] == 0) && (D == 2 || m[2] == 0);
+      if (zero) {
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) v[cc][i] = keep * v[cc][i] + ld2<T>(cf.kz_src[cc]);
+      } else {
+        cx<T> nv[3];
+        const T nrm = mode_symbol_d<T, D>(a, m, nv);
+        cx<T> dot = mk<T>(0, 0);
+        if (a.symbol == SYM_NETWORK) {
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) dot = dot + conj(nv[cc]) * v[cc][i];
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < D; ++cc) dot = dot + nv[cc] * v[cc][i];
+        }
+        const T inv = (T)1 / nrm;
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) v[cc][i] = ga * v[cc][i] + gb * (inv * (nv[cc] * dot));
+      }
+    }
+  }
+  if (a.mode != 1) {
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) {
+      reg_fft<T, N, R, SH::PAD>(v[cc], slot, j, (T)1, tw);
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc)
+#pragma unroll
+      for (int i = 0; i < R; ++i) X[cc * M + (long long)(j + TL * i) * a.stride] = v[cc][i];
+  }
+}
+
+}  // namespace scfft

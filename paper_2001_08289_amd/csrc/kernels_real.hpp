@@ -1,0 +1,276 @@
+// Real-field mode (real sigma1, real graded medium).
+//
+// With real sigma1 every scheme keeps its fields real: MS, EM and the power /
+// adjoint iterations have real local coefficients, and in H'' (eqs. J27-J37)
+// p1 is real while p2, p3 are imaginary, so Q stays real and S, T stay
+// imaginary; they are stored as S' = S/i, T' = T/i with
+//   s = p1 Q - q2 S' - q3 T'   (q2 = Im p2, q3 = Im p3),
+//   S' <- -z (2 q2 s - S'),  T' <- z (2 q3 s - T'),
+// the same algebra as the complex form of eq. J36 / J44.
+//
+// Layout: real-space arrays (E_prev, S', T') are real [b][c][N^d]; the iterate
+// X is stored as the Hermitian half of its x-direction spectrum,
+// kx = 0..n0/2, rows of H = n0/2 + 1 complex values ([b][c][H n1 n2]).
+// Two real rows of one component share one complex FFT of length n0:
+// w = a + i b, and a, b are recovered from w(k) and w(n0 - k).
+#pragma once
+
+#include "kernels_p2.hpp"
+
+namespace scfft {
+
+template <typename T, int MK>
+struct LocalMapR {
+  int iter, kind;
+  T cE[2], cO[2], cJ[2], cS[2];
+  T s1, s0, p1, q2, q3, z, inv1w, p1kap;
+  T invM, e0c;
+  const uint8_t* phase;
+  const double* dens;
+  T* S;
+  T* Tt;
+  T* Ep;
+
+  __device__ __forceinline__ void load(const XArgs& a, int solve, int comp, long long rbase) {
+    const SolveCoef& cf = a.coef[solve];
+    const SolveCtl& ctl = a.ctl[solve];
+    iter = ctl.iter;
+    kind = cf.kind;
+    for (int ph = 0; ph < 2; ++ph) {
+      cE[ph] = (T)cf.cE[ph][0];
+      cO[ph] = (T)cf.cO[ph][0];
+      cJ[ph] = (T)cf.cJ[ph][0];
+      cS[ph] = (T)cf.cS[ph][0];
+    }
+    s1 = (T)cf.s1[0];
+    s0 = (T)cf.s0[0];
+    p1 = (T)cf.p[0][0];
+    q2 = (T)cf.p[1][1];
+    q3 = (T)cf.p[2][1];
+    z = (T)cf.z[0];
+    inv1w = (T)cf.inv1w[0];
+    p1kap = (T)cf.p1kap[0];
+    invM = (T)a.invM;
+    e0c = (T)ctl.e0[comp];
+    phase = a.phase;
+    dens = a.density;
+    S = a.Sslot ? reinterpret_cast<T*>(a.Sslot) + rbase : nullptr;
+    Tt = a.Tslot ? reinterpret_cast<T*>(a.Tslot) + rbase : nullptr;
+    Ep = reinterpret_cast<T*>(a.Eprev) + rbase;
+  }
+
+  __device__ __forceinline__ T apply(T raw, long long g, Acc& acc) const {
+    const T x = invM * raw;
+    T E, J, out;
+    if (MK == MAP_ACC_EM) {
+      if (phase[g]) {
+        const T sv = S[g], tv = Tt[g];
+        const T s = p1 * x - q2 * sv - q3 * tv;
+        E = inv1w * x + p1kap * s;
+        J = s1 * E;
+        out = z * ((T)2 * p1 * s - x);
+        S[g] = -z * ((T)2 * q2 * s - sv);
+        Tt[g] = z * ((T)2 * q3 * s - tv);
+      } else {
+        E = inv1w * x;
+        J = E;
+        out = -z * x;
+      }
+    } else if (MK == MAP_ACC_MS) {
+      E = x;
+      if (phase[g]) {
+        const T sv = S[g];
+        const T s = p1 * x - q2 * sv;
+        J = s1 * E;
+        out = z * (x - (T)2 * p1 * s);
+        S[g] = z * (sv - (T)2 * q2 * s);
+      } else {
+        J = E;
+        out = z * x;
+      }
+    } else {
+      T ce, co, cj, cs;
+      if (MK == MAP_LIN_DENS) {
+        const T rho = (T)dens[g];
+        const T sig = (T)1 + (s1 - (T)1) * rho;
+        if (kind == K_MS) {
+          ce = (T)1;
+          co = (T)1 - sig / s0;
+          cj = sig;
+          cs = (T)0;
+        } else if (kind == K_EM) {
+          ce = (T)1 / (sig + s0);
+          co = (sig - s0) * ce;
+          cj = sig;
+          cs = (T)0;
+        } else {   // adjoint
+          ce = (T)1;
+          co = (sig - s0) / (sig + s0);
+          cj = (T)0;
+          cs = sig / (sig + s0);
+        }
+      } else {
+        const bool ph = phase[g] != 0;
+        ce = ph ? cE[1] : cE[0];
+        co = ph ? cO[1] : cO[0];
+        cj = ph ? cJ[1] : cJ[0];
+        cs = ph ? cS[1] : cS[0];
+      }
+      E = ce * x;
+      J = cj * E;
+      out = co * x + cs * e0c;
+    }
+    acc.Jr += (double)J;
+    acc.e2 += (double)(E * E);
+    acc.eJ += (double)(E * J);
+    if (iter >= 1) {
+      const T dE = E - Ep[g];
+      acc.d2 += (double)(dE * dE);
+    }
+    Ep[g] = E;
+    return out;
+  }
+};
+
+// x pass, real mode: LINES complex lines = 2*LINES real rows of one component.
+template <typename T, int N, int R, int MK>
+__global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArgs a) {
+  using SH = XPassShape<N, R>;
+  constexpr int TL = SH::TL, LINES = SH::LINES, NTH = SH::NTH;
+  constexpr int LP = P2Plan<N, R>::LP;
+  constexpr int H = N / 2 + 1;
+  const int solve = blockIdx.z;
+  const int comp = blockIdx.y;
+  if (!a.ignore_done && a.ctl[solve].done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x;
+  const int line = tid / TL;
+  const int j = tid - line * TL;
+  const long long pr = (long long)blockIdx.x * LINES + line;
+  const bool valid = pr < a.nlines / 2;
+  const long long rowA = 2 * pr, rowB = 2 * pr + 1;
+  const long long cbase = (long long)solve * a.d + comp;
+  cx<T>* XA = reinterpret_cast<cx<T>*>(a.X) + cbase * a.Mh + rowA * H;
+  cx<T>* XB = XA + H;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  cx<T> v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int k = j + TL * i;
+    cx<T> av = mk<T>(0, 0), bv = mk<T>(0, 0);
+    if (valid) {
+      if (k <= N / 2) {
+        av = XA[k];
+        bv = XB[k];
+      } else {
+        av = conj(XA[N - k]);
+        bv = conj(XB[N - k]);
+      }
+    }
+    v[i] = mk<T>(av.x - bv.y, av.y + bv.x);   // a + i b
+  }
+  cx<T>* slot = lds + line * LP;
+  reg_fft<T, N, R>(v, slot, j, (T)1, tw);
+  LocalMapR<T, MK> lm;
+  lm.load(a, solve, comp, cbase * a.M);
+  Acc acc;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const long long k = j + TL * i;
+      const T oa = lm.apply(v[i].x, rowA * N + k, acc);
+      const T ob = lm.apply(v[i].y, rowB * N + k, acc);
+      v[i] = mk<T>(oa, ob);
+    }
+  }
+  reg_fft<T, N, R>(v, slot, j, (T)-1, tw);
+  // split w(k) into the half spectra of the two rows: needs w(N - k)
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < R; ++i) slot[lpad<true>(j + TL * i)] = v[i];
+  __syncthreads();
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int k = j + TL * i;
+      if (k <= N / 2) {
+        const cx<T> wn = conj(slot[lpad<true>((N - k) & (N - 1))]);
+        const cx<T> s = v[i] + wn, dd = v[i] - wn;
+        XA[k] = mk<T>((T)0.5 * s.x, (T)0.5 * s.y);
+        XB[k] = mk<T>((T)0.5 * dd.y, (T)-0.5 * dd.x);
+      }
+    }
+  }
+  __syncthreads();
+  block_reduce5<NTH>(acc, reinterpret_cast<double*>(smem_raw),
+                     a.part + (cbase * gridDim.x + blockIdx.x) * 5, tid);
+}
+
+struct InitRArgs {
+  void* X;
+  void* Sslot;
+  void* Tslot;
+  SolveCtl* ctl;
+  const SolveCoef* coef;
+  long long M, Mh;
+  int d, H, nsolve, has_st;
+};
+
+// X^0 = constant c per component: half spectrum M*c at kx = 0 of every row.
+template <typename T>
+__global__ void init_real_kernel(InitRArgs a) {
+  const long long totx = (long long)a.nsolve * a.d * a.Mh;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < totx;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long f = i / a.Mh;
+    const long long g = i - f * a.Mh;
+    const int c = (int)(f % a.d);
+    const int s = (int)(f / a.d);
+    cx<T> v = mk<T>(0, 0);
+    if (g % a.H == 0) v = mk<T>((T)a.coef[s].init_src[c][0], (T)0);
+    reinterpret_cast<cx<T>*>(a.X)[i] = v;
+  }
+  if (a.has_st) {
+    const long long tot = (long long)a.nsolve * a.d * a.M;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (long long)gridDim.x * blockDim.x) {
+      reinterpret_cast<T*>(a.Sslot)[i] = (T)0;
+      reinterpret_cast<T*>(a.Tslot)[i] = (T)0;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x < a.nsolve) {
+    SolveCtl* c = a.ctl + threadIdx.x;
+    c->iter = 0;
+    c->done = 0;
+    c->status = -3;
+    c->since_min = 0;
+    c->min_r = __builtin_inf();
+    c->res = __builtin_nan("");
+  }
+}
+
+template <typename T>
+__global__ void extract_real_kernel(ExtractArgs a) {
+  const long long tot = (long long)a.d * a.M;
+  const SolveCoef& cf = a.coef[a.solve];
+  const T* src = reinterpret_cast<const T*>(a.Eprev) + (long long)a.solve * a.d * a.M;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long g = i % a.M;
+    const double e = (double)src[i];
+    if (a.E) {
+      a.E[2 * i] = e;
+      a.E[2 * i + 1] = 0.0;
+    }
+    if (a.J) {
+      double sig;
+      if (cf.density) sig = 1.0 + (cf.s1[0] - 1.0) * a.density[g];
+      else sig = a.phase[g] ? cf.s1[0] : 1.0;
+      a.J[2 * i] = sig * e;
+      a.J[2 * i + 1] = 0.0;
+    }
+  }
+}
+
+}  // namespace scfft

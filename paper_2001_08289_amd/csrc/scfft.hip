@@ -17,7 +17,7 @@
 #include <tuple>
 #include <vector>
 
-#include "kernels.hpp"
+#include "kernels_real.hpp"
 #include "scfft.h"
 
 using cd = std::complex<double>;
@@ -67,6 +67,124 @@ int pow2_floor(int v) {
   return p;
 }
 
+
+bool is_p2(int n) { return n >= 16 && n <= 4096 && (n & (n - 1)) == 0; }
+
+constexpr int kR = 8;
+
+// --- register-resident launches, dispatched over the power-of-two sizes
+template <typename T, int N>
+void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
+  using SH = XPassShape<N, kR>;
+  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, kR>::LP * sizeof(cx<T>),
+                              (size_t)5 * (SH::NTH / 64) * sizeof(double));
+  switch (mk) {
+    case MAP_LIN:
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    case MAP_LIN_DENS:
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    case MAP_ACC_EM:
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    default:
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+  }
+}
+
+template <typename T, int N>
+void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
+  using SH = XPassShape<N, kR>;
+  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, kR>::LP * sizeof(cx<T>),
+                              (size_t)5 * (SH::NTH / 64) * sizeof(double));
+  switch (mk) {
+    case MAP_LIN:
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    case MAP_LIN_DENS:
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    case MAP_ACC_EM:
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    default:
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+  }
+}
+
+template <typename T, int N, int D, int CW>
+void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
+  using SH = LineShape<T, N, kR, CW>;
+  const size_t lds = (size_t)SH::C * SH::LP * sizeof(cx<T>);
+  hipLaunchKernelGGL((line_p2_kernel<T, N, kR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
+}
+
+// cw: tile width actually used (one of the instantiated widths).
+template <typename T, int N, int D>
+void launch_line_p2(const GArgs& a, dim3 grid, hipStream_t st) {
+  switch (a.C) {
+    case 1: launch_line_p2_cw<T, N, D, 1>(a, grid, st); break;
+    case 2: launch_line_p2_cw<T, N, D, 2>(a, grid, st); break;
+    case 4: launch_line_p2_cw<T, N, D, 4>(a, grid, st); break;
+    case 8: launch_line_p2_cw<T, N, D, 8>(a, grid, st); break;
+    default: launch_line_p2_cw<T, N, D, 0>(a, grid, st); break;
+  }
+}
+
+template <int N>
+int xlines_p2() { return XPassShape<N, kR>::LINES; }
+template <typename T, int N>
+int linec_p2() { return LineShape<T, N, kR>::C; }
+
+// Tile width of the strided passes: the widest that fits, or a narrower one
+// from SCFFT_LINE_C (a power of two) for tuning.
+int tuned_c(int cmax) {
+  const char* e = std::getenv("SCFFT_LINE_C");
+  if (!e) return cmax;
+  const int v = std::atoi(e);
+  if (v == 1 || v == 2 || v == 4 || v == 8) return std::min(v, cmax);
+  return cmax;
+}
+
+#define SCFFT_P2_SWITCH(n, CALL) \
+  switch (n) {                   \
+    case 16: CALL(16); break;    \
+    case 32: CALL(32); break;    \
+    case 64: CALL(64); break;    \
+    case 128: CALL(128); break;  \
+    case 256: CALL(256); break;  \
+    case 512: CALL(512); break;  \
+    case 1024: CALL(1024); break; \
+    case 2048: CALL(2048); break; \
+    case 4096: CALL(4096); break; \
+    default: break;              \
+  }
+
+int p2_xlines(int n) {
+  int r = 1;
+#define C_(N) r = xlines_p2<N>()
+  SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  return r;
+}
+
+int p2_linec(int n, int prec) {
+  int r = 1;
+  if (prec == SCFFT_FP32) {
+#define C_(N) r = linec_p2<float, N>()
+    SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  } else {
+#define C_(N) r = linec_p2<double, N>()
+    SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  }
+  return r;
+}
+
 struct Plan {
   int dev = 0, d = 2, n[3] = {1, 1, 1}, prec = 0, nsolve = 1, symbol = 0;
   bool st = false;
@@ -77,6 +195,9 @@ struct Plan {
   void* S = nullptr;
   void* T = nullptr;
   double* part = nullptr;
+  double* part2 = nullptr;
+  unsigned int* count = nullptr;
+  int fgroups = 1;
   SolveCtl* ctl = nullptr;
   SolveCoef* coef = nullptr;
   double* hist_r = nullptr;
@@ -87,9 +208,20 @@ struct Plan {
   FftDesc fd[3];
   int xlines = 0, xL = 1, xblocks = 0;
   int gC = 1, yC = 1;
+  bool p2x = false, p2g = false, p2y = false;   // register-resident passes
+  int mk = MAP_LIN;                              // local map of the current solves
+  bool real = false;                             // real-field mode (half spectra)
+  int H = 0;                                     // stored x-spectrum length
+  long long Mh = 0;                              // stored elements per component of X
 };
 
-using PlanKey = std::tuple<int, int, int, int, int, int, int, bool, int, int>;
+int map_kind(int kind, bool density) {
+  if (kind == K_ACC_EM) return MAP_ACC_EM;
+  if (kind == K_ACC_MS) return MAP_ACC_MS;
+  return density ? MAP_LIN_DENS : MAP_LIN;
+}
+
+using PlanKey = std::tuple<int, int, int, int, int, int, int, bool, int, int, bool>;
 std::map<PlanKey, Plan*> g_plans;
 std::mutex g_mutex;
 
@@ -98,7 +230,8 @@ void free_plan(Plan* p) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(p->dev);
-  void* ptrs[] = {p->X, p->Ep, p->S, p->T, p->part, p->ctl, p->coef, p->hist_r, p->hist_s,
+  void* ptrs[] = {p->X, p->Ep, p->S, p->T, p->part, p->part2, p->count, p->ctl, p->coef,
+                  p->hist_r, p->hist_s,
                   p->tw[0], p->tw[1], p->tw[2], p->sym[0], p->sym[1], p->sym[2]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -135,11 +268,11 @@ scfft_status ensure_hist(Plan* p, int cap) {
 
 // `slot` separates workspaces of same-shaped problems solved together.
 scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int symbol,
-                      hipStream_t stream, Plan** out, int slot = 0) {
+                      hipStream_t stream, Plan** out, int slot = 0, bool real = false) {
   int dev = 0;
   SCFFT_HIP(hipGetDevice(&dev));
   const int n2 = d == 3 ? n[2] : 1;
-  PlanKey key{dev, d, n[0], n[1], n2, prec, nsolve, st, symbol, slot};
+  PlanKey key{dev, d, n[0], n[1], n2, prec, nsolve, st, symbol, slot, real};
   auto it = g_plans.find(key);
   if (it != g_plans.end()) {
     *out = it->second;
@@ -157,27 +290,50 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->symbol = symbol;
   p->M = (long long)n[0] * n[1] * n2;
   p->esz = prec == SCFFT_FP32 ? 8 : 16;
+  p->real = real;
+  p->H = real ? n[0] / 2 + 1 : n[0];
+  p->Mh = (long long)p->H * n[1] * n2;
   const int el = elems_for(prec);
-  p->xlines = (int)(p->M / n[0]);
-  p->xL = std::max(1, std::min(el / n[0], p->xlines));
-  p->xblocks = (p->xlines + p->xL - 1) / p->xL;
   const int nlast = n[d - 1];
-  p->gC = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
-  p->yC = d == 3 ? std::min(pow2_floor(std::max(1, el / n[1])), n[0]) : 1;
+  p->xlines = (int)(p->M / n[0]);
+  p->p2x = is_p2(n[0]) && !std::getenv("SCFFT_NO_P2");
+  p->p2g = is_p2(nlast) && !std::getenv("SCFFT_NO_P2") && (d == 2 || nlast <= 1024);
+  p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
+  if (p->p2x) {
+    p->xL = p2_xlines(n[0]);
+  } else {
+    p->xL = std::max(1, std::min(el / n[0], p->xlines));
+  }
+  p->xblocks = real ? (p->xlines / 2 + p->xL - 1) / p->xL : (p->xlines + p->xL - 1) / p->xL;
+  p->gC = p->p2g ? tuned_c(p2_linec(nlast, prec))
+                 : std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
+  p->yC = d == 3 ? (p->p2y ? tuned_c(p2_linec(n[1], prec))
+                           : std::min(pow2_floor(std::max(1, el / n[1])), n[0]))
+                 : 1;
   const size_t field = (size_t)nsolve * d * p->M * p->esz;
+  // real mode: X holds half spectra, the real-space arrays hold real values
+  const size_t xfield = real ? (size_t)nsolve * d * p->Mh * p->esz : field;
+  const size_t rfield = real ? field / 2 : field;
   auto fail = [&](hipError_t e) {
     free_plan(p);
     return e == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;
   };
   hipError_t e;
-  if ((e = hipMalloc(&p->X, field)) != hipSuccess) return fail(e);
-  if ((e = hipMalloc(&p->Ep, field)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&p->X, xfield)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&p->Ep, rfield)) != hipSuccess) return fail(e);
   if (st) {
-    if ((e = hipMalloc(&p->S, field)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc(&p->T, field)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&p->S, rfield)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&p->T, rfield)) != hipSuccess) return fail(e);
   }
   if ((e = hipMalloc(&p->part, sizeof(double) * 5 * (size_t)nsolve * d * p->xblocks)) != hipSuccess)
     return fail(e);
+  if ((e = hipMalloc(&p->part2, sizeof(double) * 64 * 9 * (size_t)nsolve)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMalloc(&p->count, sizeof(unsigned int) * (size_t)nsolve)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMemsetAsync(p->count, 0, sizeof(unsigned int) * (size_t)nsolve, stream)) != hipSuccess)
+    return fail(e);
+  p->fgroups = std::max(1, std::min(64, (p->xblocks * d + 127) / 128));
   if ((e = hipMalloc(&p->ctl, sizeof(SolveCtl) * nsolve)) != hipSuccess) return fail(e);
   if ((e = hipMalloc(&p->coef, sizeof(SolveCoef) * nsolve)) != hipSuccess) return fail(e);
   for (int a = 0; a < d; ++a) {
@@ -398,6 +554,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     a.tw = p->tw[0];
     a.fd = p->fd[0];
     a.M = p->M;
+    a.Mh = p->Mh;
     a.n0 = p->n[0];
     a.nlines = p->xlines;
     a.lines_per_block = p->xL;
@@ -405,15 +562,30 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     a.invM = 1.0 / (double)p->M;
     a.ignore_done = ignore_done;
     // the x pass reuses its LDS for a 5 x (kNT/64) fp64 reduction
-    const size_t lds = std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
     rec(0);
-    hipLaunchKernelGGL((xpass_kernel<T, kNT, EMAX>), dim3(p->xblocks, d, p->nsolve), dim3(kNT),
-                       lds, st, a);
+    if (p->real) {
+      const dim3 grid(p->xblocks, d, p->nsolve);
+#define C_(N) launch_xpass_r2c<T, N>(a, grid, st, p->mk)
+      SCFFT_P2_SWITCH(p->n[0], C_)
+#undef C_
+    } else if (p->p2x) {
+      const dim3 grid(p->xblocks, d, p->nsolve);
+#define C_(N) launch_xpass_p2<T, N>(a, grid, st, p->mk)
+      SCFFT_P2_SWITCH(p->n[0], C_)
+#undef C_
+    } else {
+      const size_t lds =
+          std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
+      hipLaunchKernelGGL((xpass_kernel<T, kNT, EMAX>), dim3(p->xblocks, d, p->nsolve), dim3(kNT),
+                         lds, st, a);
+    }
     rec(1);
   }
   {
     FArgs f{};
     f.part = p->part;
+    f.part2 = p->part2;
+    f.count = p->count;
     f.ctl = p->ctl;
     f.hist_r = p->hist_r;
     f.hist_s = p->hist_s;
@@ -422,15 +594,15 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     f.invM = 1.0 / (double)p->M;
     f.ignore_done = ignore_done;
     rec(2);
-    hipLaunchKernelGGL(finalize_kernel, dim3(p->nsolve), dim3(256), 0, st, f);
+    hipLaunchKernelGGL(finalize_kernel, dim3(p->fgroups, p->nsolve), dim3(256), 0, st, f);
     rec(3);
   }
   GArgs g{};
   g.X = p->X;
   g.ctl = p->ctl;
   g.coef = p->coef;
-  g.M = p->M;
-  g.n[0] = p->n[0];
+  g.M = p->Mh;
+  g.n[0] = p->H;   // columns of X (n0, or n0/2 + 1 in real mode)
   g.n[1] = p->n[1];
   g.n[2] = p->n[2];
   g.d = d;
@@ -442,13 +614,18 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     y.tw = p->tw[1];
     y.fd = p->fd[1];
     y.C = p->yC;
-    y.stride = p->n[0];
+    y.stride = p->H;
     y.mode = 1;
-    const size_t lds = (size_t)p->n[1] * p->yC * esz;
+    const dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(4);
-    hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>),
-                       dim3((p->n[0] + p->yC - 1) / p->yC, p->n[2], p->nsolve * d), dim3(kNT), lds,
-                       st, y);
+    if (p->p2y) {
+#define C_(N) launch_line_p2<T, N, 1>(y, grid, st)
+      SCFFT_P2_SWITCH(p->n[1], C_)
+#undef C_
+    } else {
+      const size_t lds = (size_t)p->n[1] * p->yC * esz;
+      hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>), grid, dim3(kNT), lds, st, y);
+    }
     rec(5);
   }
   {
@@ -457,13 +634,31 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     q.tw = p->tw[d - 1];
     q.fd = p->fd[d - 1];
     q.C = p->gC;
-    q.stride = d == 2 ? p->n[0] : p->n[0] * p->n[1];
+    q.stride = d == 2 ? p->H : p->H * p->n[1];
     q.mode = 0;
-    const size_t lds = (size_t)nl * d * p->gC * esz;
+    const dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
     rec(6);
-    hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>),
-                       dim3((p->n[0] + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve),
-                       dim3(kNT), lds, st, q);
+    if (p->p2g) {
+      if (d == 2) {
+#define C_(N) launch_line_p2<T, N, 2>(q, grid, st)
+        SCFFT_P2_SWITCH(nl, C_)
+#undef C_
+      } else {
+        switch (nl) {
+          case 16: launch_line_p2<T, 16, 3>(q, grid, st); break;
+          case 32: launch_line_p2<T, 32, 3>(q, grid, st); break;
+          case 64: launch_line_p2<T, 64, 3>(q, grid, st); break;
+          case 128: launch_line_p2<T, 128, 3>(q, grid, st); break;
+          case 256: launch_line_p2<T, 256, 3>(q, grid, st); break;
+          case 512: launch_line_p2<T, 512, 3>(q, grid, st); break;
+          case 1024: launch_line_p2<T, 1024, 3>(q, grid, st); break;
+          default: break;
+        }
+      }
+    } else {
+      const size_t lds = (size_t)nl * d * p->gC * esz;
+      hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>), grid, dim3(kNT), lds, st, q);
+    }
     rec(7);
   }
   if (d == 3) {
@@ -471,13 +666,18 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     y.tw = p->tw[1];
     y.fd = p->fd[1];
     y.C = p->yC;
-    y.stride = p->n[0];
+    y.stride = p->H;
     y.mode = 2;
-    const size_t lds = (size_t)p->n[1] * p->yC * esz;
+    const dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(8);
-    hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>),
-                       dim3((p->n[0] + p->yC - 1) / p->yC, p->n[2], p->nsolve * d), dim3(kNT), lds,
-                       st, y);
+    if (p->p2y) {
+#define C_(N) launch_line_p2<T, N, 1>(y, grid, st)
+      SCFFT_P2_SWITCH(p->n[1], C_)
+#undef C_
+    } else {
+      const size_t lds = (size_t)p->n[1] * p->yC * esz;
+      hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>), grid, dim3(kNT), lds, st, y);
+    }
     rec(9);
   }
   SCFFT_HIP(hipGetLastError());
@@ -492,6 +692,29 @@ scfft_status launch_iteration(Plan* p, const uint8_t* phase, const double* densi
 }
 
 scfft_status launch_init(Plan* p, hipStream_t st) {
+  if (p->nsolve > 256) return SCFFT_ERR_INVALID_ARG;
+  if (p->real) {
+    InitRArgs r{};
+    r.X = p->X;
+    r.Sslot = p->S;
+    r.Tslot = p->T;
+    r.ctl = p->ctl;
+    r.coef = p->coef;
+    r.M = p->M;
+    r.Mh = p->Mh;
+    r.d = p->d;
+    r.H = p->H;
+    r.nsolve = p->nsolve;
+    r.has_st = p->st ? 1 : 0;
+    const long long tot = (long long)p->nsolve * p->d * p->M;
+    const int blocks = (int)std::min<long long>((tot + 255) / 256, 65536);
+    if (p->prec == SCFFT_FP32)
+      hipLaunchKernelGGL(init_real_kernel<float>, dim3(blocks), dim3(256), 0, st, r);
+    else
+      hipLaunchKernelGGL(init_real_kernel<double>, dim3(blocks), dim3(256), 0, st, r);
+    SCFFT_HIP(hipGetLastError());
+    return SCFFT_OK;
+  }
   InitArgs a{};
   a.X = p->X;
   a.Sslot = p->S;
@@ -530,10 +753,16 @@ scfft_status launch_extract(Plan* p, int solve, const uint8_t* phase, const doub
   a.solve = solve;
   const long long tot = (long long)p->d * p->M;
   const int blocks = (int)std::min<long long>((tot + 255) / 256, 65536);
-  if (p->prec == SCFFT_FP32)
+  if (p->real) {
+    if (p->prec == SCFFT_FP32)
+      hipLaunchKernelGGL(extract_real_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL(extract_real_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+  } else if (p->prec == SCFFT_FP32) {
     hipLaunchKernelGGL(extract_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
-  else
+  } else {
     hipLaunchKernelGGL(extract_kernel<double>, dim3(blocks), dim3(256), 0, st, a);
+  }
   SCFFT_HIP(hipGetLastError());
   return SCFFT_OK;
 }
@@ -657,6 +886,22 @@ cd graded_sigma0(int scheme, cd s1) {
   return std::sqrt(s1);
 }
 
+// Real-field mode: every coefficient real, a power-of-two x length and an
+// even number of x lines (rows are transformed in pairs).
+bool real_ok(const SolveSpec& sp, int d, const int* n) {
+  if (std::getenv("SCFFT_NO_REAL")) return false;
+  if (!is_p2(n[0])) return false;
+  const long long lines = (long long)n[1] * (d == 3 ? n[2] : 1);
+  if (lines % 2) return false;
+  if (sp.s1.imag() != 0.0 || sp.s0.imag() != 0.0) return false;
+  if (sp.kind == K_ACC_EM || sp.kind == K_ACC_MS) {
+    if (sp.sc.t.imag() != 0.0 || !(sp.sc.t.real() > 0.0)) return false;
+    if (sp.sc.p[0].imag() != 0.0 || sp.sc.p[1].real() != 0.0 || sp.sc.p[2].real() != 0.0)
+      return false;
+  }
+  return true;
+}
+
 }  // namespace
 }  // namespace scfft
 
@@ -739,7 +984,8 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
   Plan* p = nullptr;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p);
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n));
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, opt->max_iter + 1);
   if (rc != SCFFT_OK) return rc;
@@ -747,6 +993,7 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   SolveCoef cf;
   fill_ctl(c, *opt, sp.kind, prob->d, prob->e0);
   fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
+  p->mk = map_kind(sp.kind, prob->density != nullptr);
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);
@@ -784,8 +1031,10 @@ scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scff
   std::vector<const uint8_t*> ph(nprob);
   std::vector<const double*> de(nprob);
   for (int i = 0; i < nprob; ++i) {
+    bool real = true;
+    for (int j = 0; j < nsig; ++j) real = real && real_ok(specs[i][j], probs[i].d, probs[i].n);
     scfft_status rc = get_plan(probs[i].d, probs[i].n, o0.precision, nsig, any_acc, o0.symbol, st,
-                               &plans[i], i);
+                               &plans[i], i, real);
     if (rc != SCFFT_OK) return rc;
     rc = ensure_hist(plans[i], o0.max_iter + 1);
     if (rc != SCFFT_OK) return rc;
@@ -796,6 +1045,10 @@ scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scff
       fill_coef(cf[j], specs[i][j], probs[i].density != nullptr, probs[i].d, probs[i].e0,
                 (double)plans[i]->M);
     }
+    plans[i]->mk = map_kind(specs[i][0].kind, probs[i].density != nullptr);
+    for (int j = 1; j < nsig; ++j)
+      if (map_kind(specs[i][j].kind, probs[i].density != nullptr) != plans[i]->mk)
+        return SCFFT_ERR_INVALID_ARG;
     SCFFT_HIP(hipMemcpyAsync(plans[i]->ctl, c.data(), sizeof(SolveCtl) * nsig,
                              hipMemcpyHostToDevice, st));
     SCFFT_HIP(hipMemcpyAsync(plans[i]->coef, cf.data(), sizeof(SolveCoef) * nsig,
@@ -829,7 +1082,10 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
   std::lock_guard<std::mutex> lk(g_mutex);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Plan* p = nullptr;
-  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 2, false, symbol, st, &p);
+  SolveSpec pw{};
+  pw.kind = K_POWER;
+  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 2, false, symbol, st, &p, 0,
+                real_ok(pw, prob->d, prob->n));
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, iters + 2);
   if (rc != SCFFT_OK) return rc;
@@ -849,6 +1105,7 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
     fill_ctl(c[k], o, K_POWER, prob->d, e0);
     fill_coef(cf[k], sp, false, prob->d, e0, (double)p->M);
   }
+  p->mk = MAP_LIN;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);
@@ -905,7 +1162,8 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
   {
     std::lock_guard<std::mutex> lk(g_mutex);
     Plan* p = nullptr;
-    rc = get_plan(prob->d, prob->n, o.precision, 1, false, o.symbol, st, &p);
+    rc = get_plan(prob->d, prob->n, o.precision, 1, false, o.symbol, st, &p, 0,
+                  real_ok(sp, prob->d, prob->n));
     if (rc == SCFFT_OK) rc = ensure_hist(p, o.max_iter + 1);
     for (int pass = 0; pass < 2 && rc == SCFFT_OK; ++pass) {
       SolveSpec s = sp;
@@ -914,6 +1172,7 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
       SolveCoef cf;
       fill_ctl(c, o, s.kind, prob->d, prob->e0);
       fill_coef(cf, s, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
+      p->mk = map_kind(s.kind, prob->density != nullptr);
       if (hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st) != hipSuccess ||
           hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st) != hipSuccess) {
         rc = SCFFT_ERR_DEVICE;
@@ -952,10 +1211,17 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
       a.scale = 1.0 / ((double)M * n2);
       a.M = M;
       a.d = prob->d;
-      if (o.precision == SCFFT_FP32)
-        hipLaunchKernelGGL(gradient_kernel<float>, dim3(gblocks), dim3(256), 0, st, a);
-      else
-        hipLaunchKernelGGL(gradient_kernel<double>, dim3(gblocks), dim3(256), 0, st, a);
+      if (o.precision == SCFFT_FP32) {
+        if (p->real)
+          hipLaunchKernelGGL((gradient_kernel<float, true>), dim3(gblocks), dim3(256), 0, st, a);
+        else
+          hipLaunchKernelGGL((gradient_kernel<float, false>), dim3(gblocks), dim3(256), 0, st, a);
+      } else {
+        if (p->real)
+          hipLaunchKernelGGL((gradient_kernel<double, true>), dim3(gblocks), dim3(256), 0, st, a);
+        else
+          hipLaunchKernelGGL((gradient_kernel<double, false>), dim3(gblocks), dim3(256), 0, st, a);
+      }
       hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, st, part, gblocks, sum);
       double hs[2] = {0, 0};
       if (hipGetLastError() != hipSuccess ||
@@ -1001,7 +1267,8 @@ scfft_status scfft_profile_passes(const scfft_problem* prob, const scfft_options
   hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
   Plan* p = nullptr;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p);
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n));
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, iters + 2);
   if (rc != SCFFT_OK) return rc;
@@ -1012,6 +1279,7 @@ scfft_status scfft_profile_passes(const scfft_problem* prob, const scfft_options
   SolveCoef cf;
   fill_ctl(c, o, sp.kind, prob->d, prob->e0);
   fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
+  p->mk = map_kind(sp.kind, prob->density != nullptr);
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);

@@ -222,3 +222,24 @@ def test_autograd_function_matches_finite_differences():
     fd = (f(rho.detach() + eps * direction) - f(rho.detach() - eps * direction)) / (2 * eps)
     an = (rho.grad * direction).sum().item()
     assert abs(fd - an) < 1e-6 * abs(an)
+
+
+@pytest.mark.parametrize("path", ["real", "complex", "generic"])
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("shape", [(64, 128), (16, 32, 64)])
+def test_execution_paths_agree(path, scheme, shape, monkeypatch):
+    """The real-field (half-spectrum), complex register-resident and generic
+    LDS-staged paths each match the oracle on the same case."""
+    if path != "real":
+        monkeypatch.setenv("SCFFT_NO_REAL", "1")
+    if path == "generic":
+        monkeypatch.setenv("SCFFT_NO_P2", "1")
+    scfft.release()
+    try:
+        chi = inputs.random_phase(shape, 0.3, seed=3)
+        got, ref = _fixed(chi, 10.0, scheme, 5)
+        assert _field_err(got, ref) < 1e-11
+        got, ref = _fixed(chi, 10.0, scheme, 5, precision="fp32")
+        assert _field_err(got, ref) < 2e-6
+    finally:
+        scfft.release()

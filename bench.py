@@ -33,22 +33,28 @@ HEADLINE = dict(scheme="acc_em", precision="fp32", sigma1=100.0)
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(scheme: str, precision: str, d: int, frac1: float):
+def algorithmic_bytes(scheme: str, precision: str, d: int, frac1: float, n0: int,
+                      real: bool = True):
     """Bytes one voxel moves through HBM in each kernel of one iteration.
 
-    x pass: read + write the iterate (d complex), read + write the previous
-    physical field (d complex, for the relative increment), the phase byte,
-    and for the H'' schemes read + write of the S, T slots at phase-1 voxels
-    (2 slots for EM in H'', 1 for MS in H'').  Gamma pass: read + write the
-    iterate.  3D adds two plain y passes of the same size as the Gamma pass.
+    x pass: read + write of the iterate X (d components; real-field mode
+    stores the half spectrum, (n0/2+1)/n0 complex values per voxel), read +
+    write of the previous physical field (real in real-field mode), the phase
+    byte, and for the H'' schemes read + write of the S, T slots at phase-1
+    voxels (2 slots for EM in H'', 1 for MS in H'').  Gamma pass: read + write
+    of X.  3D adds two plain y passes of the same size as the Gamma pass.
     """
-    c = 8 if precision == "fp32" else 16
-    xp = 4 * d * c + 1
-    if scheme == "acc_em":
-        xp += 2 * 2 * d * c * frac1
-    elif scheme == "acc_ms":
-        xp += 2 * d * c * frac1
-    gp = 2 * d * c
+    c = 4 if precision == "fp32" else 8          # bytes of one real value
+    if real:
+        xs = d * (n0 // 2 + 1) / n0 * 2 * c       # X per voxel (complex half spectrum)
+        ep = d * c                                 # real-space field per voxel
+    else:
+        xs = d * 2 * c
+        ep = d * 2 * c
+    xp = 2 * xs + 2 * ep + 1
+    slots = {"acc_em": 2, "acc_ms": 1}.get(scheme, 0)
+    xp += 2 * slots * ep * frac1
+    gp = 2 * xs
     return {"xpass": xp, "gamma": gp, "y": gp if d == 3 else 0.0}
 
 
@@ -120,9 +126,14 @@ def extra_configs(scfft, inputs, torch) -> dict:
         # every solve is iterated until the slowest of the batch stops; the
         # voxel-iterations counted here are the useful ones (up to each stop)
         useful = sum(n * n * int(its[i * 128:(i + 1) * 128].sum()) for i, n in enumerate(grids))
+        hist = {scfft.status_string(int(k)): int((stats == k).sum()) for k in np.unique(stats)}
+        flagged = [(int(i) // 128, int(i) % 128) for i in np.nonzero(stats != 0)[0][:8]]
         res[prec] = {"wall_s": round(wall, 3), "useful_voxel_iters_per_s": useful / wall,
                      "iterations_min_mean_max": [int(its.min()), float(its.mean()), int(its.max())],
-                     "converged": int((stats == 0).sum()), "flagged": int((stats != 0).sum())}
+                     "status_counts": hist,
+                     "flagged_examples": [{"structure": a, "j": b, "sigma1": str(np.round(sig[a][b], 4)),
+                                           "iterations": int(its[a * 128 + b]),
+                                           "residual": rs[a * 128 + b]["residual"]} for a, b in flagged]}
         log("batch", prec, res[prec])
         scfft.release()
     out["disk_batch"] = {"solves": len(rs), "voxels_per_batch_iteration": vox,
@@ -195,6 +206,14 @@ def main() -> int:
 
     hs = HEADLINE
     if args.profile_only:
+        # calibration for the HBM byte counters: a 256 MiB fill, then a
+        # 256 MiB read + 256 MiB write copy
+        cal_x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        cal_x.fill_(1.0)
+        cal_y = torch.empty_like(cal_x)
+        cal_y.copy_(cal_x)
+        torch.cuda.synchronize()
+        del cal_x, cal_y
         prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
                                     alpha=0.25, beta=4.0, iters=args.profile_iters)
         print(json.dumps({"profile": prof, "config": hs, "grid": [N, N]}), flush=True)
@@ -219,7 +238,7 @@ def main() -> int:
     # ---------------------------------------------------------- roofline
     prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
                                 alpha=0.25, beta=4.0, iters=args.profile_iters)
-    ab = algorithmic_bytes(hs["scheme"], hs["precision"], 2, frac1)
+    ab = algorithmic_bytes(hs["scheme"], hs["precision"], 2, frac1, N, real=True)
     kern = {k: {"ms": round(prof[k], 5),
                 "GB/s": round(ab[k] * N * N / (prof[k] * 1e-3) / 1e9, 1) if prof[k] > 0 else None}
             for k in ("xpass", "gamma")}

@@ -25,7 +25,7 @@ enum Kind { K_MS = 0, K_EM = 1, K_ACC_EM = 2, K_ACC_MS = 3, K_POWER = 4, K_ADJ =
 enum Sym { SYM_ROTATED = 0, SYM_SPECTRAL = 1, SYM_NETWORK = 2 };
 
 // Per-solve control block (device resident).  The host writes the parameter
-// part before a solve; finalize_kernel owns the state part afterwards.
+// part before a solve; finalize_solve owns the state part afterwards.
 struct SolveCtl {
   double tol, div_factor;
   int max_iter, stag_window;
@@ -78,6 +78,18 @@ struct XArgs {
   int ignore_done;
 };
 
+// Reduction inputs of the stop rules (see finalize_solve).
+struct FArgs {
+  const double* part;
+  SolveCtl* ctl;
+  double* hist_r;
+  double* hist_s;
+  int hist_cap;
+  int nblocks;     // x-pass workgroups per component
+  double invM;
+  int ignore_done;
+};
+
 struct GArgs {
   void* X;
   SolveCtl* ctl;
@@ -90,7 +102,11 @@ struct GArgs {
   int d, C, stride, symbol;
   int ignore_done;
   int mode;             // 0: Gamma pass; 1: forward FFT only; 2: inverse FFT only
+  int fin;              // 1: workgroup (0,0) of each solve also runs finalize_solve
+  FArgs f;
 };
+
+__device__ __forceinline__ void finalize_solve(const FArgs& a, int solve, int tid, int nth);
 
 template <typename T>
 __device__ __forceinline__ cx<T> ld2(const double* p) { return mk<T>((T)p[0], (T)p[1]); }
@@ -362,10 +378,13 @@ __global__ __launch_bounds__(NT) void line_pass_kernel(GArgs a) {
   const int comp0 = gam ? 0 : blockIdx.z % d;
   const int ncomp = gam ? d : 1;
   SolveCtl* ctl = a.ctl + solve;
+  // done was set by an earlier kernel (or, harmlessly, by this one's
+  // finalizing workgroup: a stale read only costs a wasted tile)
   if (!a.ignore_done && ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
+  if (a.fin && blockIdx.x == 0 && blockIdx.y == 0 && comp0 == 0) finalize_solve(a.f, solve, tid, NT);
   const int C = a.C;
   const int N = a.fd.n;
   const int x0 = blockIdx.x * C;
@@ -438,80 +457,11 @@ __global__ __launch_bounds__(NT) void line_pass_kernel(GArgs a) {
 }
 
 // ---------------------------------------------------------------- finalize
-struct FArgs {
-  const double* part;
-  double* part2;       // [solve][groups][9] second-level sums
-  unsigned int* count; // [solve] groups finished in this launch (reset by the last)
-  SolveCtl* ctl;
-  double* hist_r;
-  double* hist_s;
-  int hist_cap;
-  int nblocks;     // x-pass workgroups per component
-  double invM;
-  int ignore_done;
-};
 
-// Reduction and stop rules.  Grid (groups, solves): every group sums a fixed
-// slice of the x-pass partials, the last group to finish (device-scope
-// counter) adds the group sums in fixed order and applies the stop rules, so
-// the result does not depend on scheduling.
-__global__ __launch_bounds__(256) void finalize_kernel(FArgs a) {
-  const int solve = blockIdx.y;
-  const int grp = blockIdx.x;
-  const int ngrp = gridDim.x;
-  SolveCtl* ctl = a.ctl + solve;
-  if (!a.ignore_done && ctl->done) return;
+// Stop rules (converged / diverged / stagnated / max_iter) from the sums.
+__device__ __forceinline__ void finalize_status(const FArgs& a, SolveCtl* ctl, const double* tot) {
   const int d = ctl->d;
-  __shared__ double red[9][4];
-  __shared__ double tot[9];
-  __shared__ int last;
-  const int tid = threadIdx.x;
-  const int per = (a.nblocks + ngrp - 1) / ngrp;
-  const int b0 = grp * per;
-  const int b1 = min(a.nblocks, b0 + per);
-  // per-component current sums, then |E|^2, |dE|^2, Re conj(E) J
-  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int c = 0; c < d; ++c) {
-    const double* p = a.part + ((long long)solve * d + c) * a.nblocks * 5;
-    for (int b = b0 + tid; b < b1; b += 256) {
-      acc[2 * c] += p[b * 5 + 0];
-      acc[2 * c + 1] += p[b * 5 + 1];
-      acc[6] += p[b * 5 + 2];
-      acc[7] += p[b * 5 + 3];
-      acc[8] += p[b * 5 + 4];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    double v = acc[q];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((tid & 63) == 0) red[q][tid >> 6] = v;
-  }
-  __syncthreads();
-  double* p2 = a.part2 + (long long)solve * 64 * 9;
-  if (tid < 9) {
-    const double v = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
-    __hip_atomic_store(p2 + grp * 9 + tid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned int prev = atomicAdd(a.count + solve, 1u);
-    last = (prev == (unsigned int)ngrp - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (tid < 9) {
-    double v = 0;
-    for (int g = 0; g < ngrp; ++g)
-      v += __hip_atomic_load(p2 + g * 9 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    tot[tid] = v;
-  }
-  __syncthreads();
-  if (tid != 0) return;
-  __hip_atomic_store(a.count + solve, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int solve = (int)(ctl - a.ctl);
   const int n = ctl->iter;
   double sr = 0, si = 0;
   for (int c = 0; c < d; ++c) {
@@ -576,6 +526,53 @@ __global__ __launch_bounds__(256) void finalize_kernel(FArgs a) {
   } else {
     ctl->iter = n + 1;
   }
+}
+
+// Reduction of the x-pass partials and the stop rules for one solve, run by
+// one workgroup (all its threads call it).  The partials come from the
+// previous kernel; the control block is read by the next x pass.  The sums
+// run in a fixed order, so sigma* and the residual are bit-reproducible.
+__device__ __forceinline__ void finalize_solve(const FArgs& a, int solve, int tid, int nth) {
+  SolveCtl* ctl = a.ctl + solve;
+  const int d = ctl->d;
+  __shared__ double fred[9][16];
+  __shared__ double tot[9];
+  // workgroups of fewer than 64 threads (tiny grids) sum on one thread
+  const int nt = nth >= 64 ? nth : 1;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (tid < nt) {
+    for (int c = 0; c < d; ++c) {
+      const double* p = a.part + ((long long)solve * d + c) * a.nblocks * 5;
+      for (int b = tid; b < a.nblocks; b += nt) {
+        acc[2 * c] += p[b * 5 + 0];
+        acc[2 * c + 1] += p[b * 5 + 1];
+        acc[6] += p[b * 5 + 2];
+        acc[7] += p[b * 5 + 3];
+        acc[8] += p[b * 5 + 4];
+      }
+    }
+  }
+  if (nt == 1) {
+    if (tid == 0)
+      for (int q = 0; q < 9; ++q) tot[q] = acc[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      double v = acc[q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if ((tid & 63) == 0) fred[q][tid >> 6] = v;
+    }
+    __syncthreads();
+    if (tid < 9) {
+      double v = 0;
+      for (int w = 0; w < nt / 64; ++w) v += fred[tid][w];
+      tot[tid] = v;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) finalize_status(a, ctl, tot);
+  __syncthreads();
 }
 
 // -------------------------------------------------------------------- init

@@ -106,8 +106,13 @@ struct LineShape {
   static constexpr int CF = B::C0 >= 8 ? 8 : B::C0 >= 4 ? 4 : B::C0 >= 2 ? 2 : 1;
   static constexpr int CT = 512 / TL > 0 ? 512 / TL : 1;
   static constexpr int CM = CF < CT ? CF : CT;
-  static constexpr int C = (CW > 0 && CW < CM) ? CW : CM;
-  static constexpr bool PAD = C * P2Plan<N, R>::LP * (int)sizeof(cx<T>) <= 65536;
+  static constexpr int CP = (CW > 0 && CW < CM) ? CW : CM;
+  // prefer the padded layout: halve the tile until it fits (fp64 2048: 1 line)
+  static constexpr int PB = P2Plan<N, R>::LP * (int)sizeof(cx<T>);
+  static constexpr int C = (CP * PB <= 65536 || CP == 1) ? CP
+                         : (CP / 2 * PB <= 65536 || CP == 2) ? CP / 2
+                         : (CP / 4 * PB <= 65536 || CP == 4) ? CP / 4 : CP / 8;
+  static constexpr bool PAD = C * PB <= 65536;
   static constexpr int LP = PAD ? P2Plan<N, R>::LP : N;
   static constexpr int NTH = TL * C;
 };
@@ -191,10 +196,16 @@ __global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(
   const int d = a.d;
   const int solve = gam ? blockIdx.z : blockIdx.z / d;
   const int comp0 = gam ? 0 : blockIdx.z % d;
+  // done was set by an earlier kernel (or, harmlessly, by this one's
+  // finalizing workgroup: a stale read only costs a wasted tile)
   if (!a.ignore_done && a.ctl[solve].done) return;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
+  // the first pass after the x pass also reduces its partials and applies
+  // the stop rules (one workgroup per solve, overlapped with the FFT tiles)
+  if (a.fin && blockIdx.x == 0 && blockIdx.y == 0 && comp0 == 0)
+    finalize_solve(a.f, solve, tid, SH::NTH);
   const int c = tid % C;
   const int j = tid / C;
   // XCD-aware tile order

@@ -195,9 +195,6 @@ struct Plan {
   void* S = nullptr;
   void* T = nullptr;
   double* part = nullptr;
-  double* part2 = nullptr;
-  unsigned int* count = nullptr;
-  int fgroups = 1;
   SolveCtl* ctl = nullptr;
   SolveCoef* coef = nullptr;
   double* hist_r = nullptr;
@@ -230,8 +227,7 @@ void free_plan(Plan* p) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(p->dev);
-  void* ptrs[] = {p->X, p->Ep, p->S, p->T, p->part, p->part2, p->count, p->ctl, p->coef,
-                  p->hist_r, p->hist_s,
+  void* ptrs[] = {p->X, p->Ep, p->S, p->T, p->part, p->ctl, p->coef, p->hist_r, p->hist_s,
                   p->tw[0], p->tw[1], p->tw[2], p->sym[0], p->sym[1], p->sym[2]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -327,13 +323,6 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   }
   if ((e = hipMalloc(&p->part, sizeof(double) * 5 * (size_t)nsolve * d * p->xblocks)) != hipSuccess)
     return fail(e);
-  if ((e = hipMalloc(&p->part2, sizeof(double) * 64 * 9 * (size_t)nsolve)) != hipSuccess)
-    return fail(e);
-  if ((e = hipMalloc(&p->count, sizeof(unsigned int) * (size_t)nsolve)) != hipSuccess)
-    return fail(e);
-  if ((e = hipMemsetAsync(p->count, 0, sizeof(unsigned int) * (size_t)nsolve, stream)) != hipSuccess)
-    return fail(e);
-  p->fgroups = std::max(1, std::min(64, (p->xblocks * d + 127) / 128));
   if ((e = hipMalloc(&p->ctl, sizeof(SolveCtl) * nsolve)) != hipSuccess) return fail(e);
   if ((e = hipMalloc(&p->coef, sizeof(SolveCoef) * nsolve)) != hipSuccess) return fail(e);
   for (int a = 0; a < d; ++a) {
@@ -581,22 +570,17 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     }
     rec(1);
   }
-  {
-    FArgs f{};
-    f.part = p->part;
-    f.part2 = p->part2;
-    f.count = p->count;
-    f.ctl = p->ctl;
-    f.hist_r = p->hist_r;
-    f.hist_s = p->hist_s;
-    f.hist_cap = p->hist_cap;
-    f.nblocks = p->xblocks;
-    f.invM = 1.0 / (double)p->M;
-    f.ignore_done = ignore_done;
-    rec(2);
-    hipLaunchKernelGGL(finalize_kernel, dim3(p->fgroups, p->nsolve), dim3(256), 0, st, f);
-    rec(3);
-  }
+  FArgs f{};
+  f.part = p->part;
+  f.ctl = p->ctl;
+  f.hist_r = p->hist_r;
+  f.hist_s = p->hist_s;
+  f.hist_cap = p->hist_cap;
+  f.nblocks = p->xblocks;
+  f.invM = 1.0 / (double)p->M;
+  f.ignore_done = ignore_done;
+  rec(2);
+  rec(3);
   GArgs g{};
   g.X = p->X;
   g.ctl = p->ctl;
@@ -608,6 +592,8 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
   g.d = d;
   g.symbol = p->symbol;
   g.ignore_done = ignore_done;
+  g.f = f;
+  g.fin = 0;
   for (int a = 0; a < d; ++a) g.symtab[a] = p->sym[a];
   if (d == 3) {
     GArgs y = g;
@@ -616,6 +602,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     y.C = p->yC;
     y.stride = p->H;
     y.mode = 1;
+    y.fin = 1;   // first pass after the x pass
     const dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(4);
     if (p->p2y) {
@@ -636,6 +623,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     q.C = p->gC;
     q.stride = d == 2 ? p->H : p->H * p->n[1];
     q.mode = 0;
+    q.fin = d == 2 ? 1 : 0;
     const dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
     rec(6);
     if (p->p2g) {
@@ -767,32 +755,127 @@ scfft_status launch_extract(Plan* p, int solve, const uint8_t* phase, const doub
   return SCFFT_OK;
 }
 
-// Iterate every solve of the given plans until all have stopped.
+// ----------------------------------------------------------- graph cache
+// One chunk of check_every iterations over all plans is captured into a HIP
+// graph and replayed until every solve has stopped.  Kernel arguments do not
+// change between iterations (the iteration state lives in device memory), so
+// a captured chunk stays valid for every later solve on the same plans and
+// input pointers; the key records everything the arguments depend on.
+struct GraphEntry {
+  std::vector<uintptr_t> key;
+  hipGraphExec_t exec = nullptr;
+};
+std::vector<GraphEntry> g_graphs;
+std::map<int, hipStream_t> g_work_streams;
+
+void free_graphs() {
+  for (auto& g : g_graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g_graphs.clear();
+}
+
+// Graph capture needs a stream other than the legacy default stream.
+scfft_status work_stream(hipStream_t st, hipStream_t* ws) {
+  if (st != nullptr) {
+    *ws = st;
+    return SCFFT_OK;
+  }
+  int dev = 0;
+  SCFFT_HIP(hipGetDevice(&dev));
+  auto it = g_work_streams.find(dev);
+  if (it == g_work_streams.end()) {
+    hipStream_t s;
+    SCFFT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    it = g_work_streams.emplace(dev, s).first;
+  }
+  *ws = it->second;
+  return SCFFT_OK;
+}
+
+scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const uint8_t*>& phases,
+                       const std::vector<const double*>& dens, int ce, hipStream_t ws,
+                       hipGraphExec_t* out) {
+  std::vector<uintptr_t> key = {(uintptr_t)ws, (uintptr_t)ce};
+  for (size_t i = 0; i < plans.size(); ++i) {
+    key.push_back((uintptr_t)plans[i]);
+    key.push_back((uintptr_t)plans[i]->mk);
+    key.push_back((uintptr_t)plans[i]->hist_r);
+    key.push_back((uintptr_t)plans[i]->hist_cap);
+    key.push_back((uintptr_t)phases[i]);
+    key.push_back((uintptr_t)dens[i]);
+  }
+  for (auto& g : g_graphs)
+    if (g.key == key) {
+      *out = g.exec;
+      return SCFFT_OK;
+    }
+  SCFFT_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
+  scfft_status rc = SCFFT_OK;
+  for (int k = 0; k < ce && rc == SCFFT_OK; ++k)
+    for (size_t i = 0; i < plans.size() && rc == SCFFT_OK; ++i)
+      rc = launch_iteration(plans[i], phases[i], dens[i], ws);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ws, &graph);
+  if (rc != SCFFT_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc != SCFFT_OK ? rc : SCFFT_ERR_DEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return SCFFT_ERR_DEVICE;
+  if (g_graphs.size() >= 32) {
+    (void)hipGraphExecDestroy(g_graphs.front().exec);
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back(GraphEntry{key, exec});
+  *out = exec;
+  return SCFFT_OK;
+}
+
+// Iterate every solve of the given plans until all have stopped.  Work made
+// earlier on `st` must be complete or ordered before the loop (callers
+// synchronise after their set-up copies).
 scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const uint8_t*>& phases,
                       const std::vector<const double*>& dens, int max_iter, int check_every,
                       hipStream_t st, double* elapsed_ms) {
+  const int ce = std::max(1, check_every);
+  const bool use_graph = !std::getenv("SCFFT_NO_GRAPH");
+  hipStream_t ws = st;
+  if (use_graph) {
+    scfft_status rc = work_stream(st, &ws);
+    if (rc != SCFFT_OK) return rc;
+    if (ws != st) SCFFT_HIP(hipStreamSynchronize(st));
+  }
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    scfft_status rc = get_graph(plans, phases, dens, ce, ws, &exec);
+    if (rc != SCFFT_OK) return rc;
+  }
   hipEvent_t e0, e1;
   SCFFT_HIP(hipEventCreate(&e0));
   SCFFT_HIP(hipEventCreate(&e1));
-  SCFFT_HIP(hipEventRecord(e0, st));
-  const int ce = std::max(1, check_every);
+  SCFFT_HIP(hipEventRecord(e0, ws));
   const long long max_chunks = (long long)(max_iter + 1) / ce + 3;
   std::vector<std::vector<SolveCtl>> host(plans.size());
   bool all_done = false;
-  scfft_status rc = SCFFT_OK;
   for (long long chunk = 0; chunk < max_chunks && !all_done; ++chunk) {
-    for (int k = 0; k < ce; ++k)
-      for (size_t i = 0; i < plans.size(); ++i) {
-        rc = launch_iteration(plans[i], phases[i], dens[i], st);
-        if (rc != SCFFT_OK) return rc;
-      }
+    if (exec) {
+      SCFFT_HIP(hipGraphLaunch(exec, ws));
+    } else {
+      for (int k = 0; k < ce; ++k)
+        for (size_t i = 0; i < plans.size(); ++i) {
+          scfft_status rc = launch_iteration(plans[i], phases[i], dens[i], ws);
+          if (rc != SCFFT_OK) return rc;
+        }
+    }
     all_done = true;
     for (size_t i = 0; i < plans.size(); ++i) {
       host[i].resize(plans[i]->nsolve);
       SCFFT_HIP(hipMemcpyAsync(host[i].data(), plans[i]->ctl, sizeof(SolveCtl) * plans[i]->nsolve,
-                               hipMemcpyDeviceToHost, st));
+                               hipMemcpyDeviceToHost, ws));
     }
-    SCFFT_HIP(hipStreamSynchronize(st));
+    SCFFT_HIP(hipStreamSynchronize(ws));
     for (size_t i = 0; i < plans.size() && all_done; ++i)
       for (const auto& c : host[i])
         if (!c.done) {
@@ -800,7 +883,7 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
           break;
         }
   }
-  SCFFT_HIP(hipEventRecord(e1, st));
+  SCFFT_HIP(hipEventRecord(e1, ws));
   SCFFT_HIP(hipEventSynchronize(e1));
   float ms = 0;
   SCFFT_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -943,6 +1026,7 @@ const char* scfft_version(void) { return "scfft 0.1 (gfx950)"; }
 
 void scfft_release(void) {
   std::lock_guard<std::mutex> lk(g_mutex);
+  free_graphs();
   for (auto& kv : g_plans) free_plan(kv.second);
   g_plans.clear();
 }

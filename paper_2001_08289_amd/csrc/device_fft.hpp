@@ -140,6 +140,42 @@ struct Dft<T, 8> {
   }
 };
 
+// 16 points as 4 x 4: DFT4 over the stride-4 subsequences, the internal
+// twiddles exp(s 2 pi i n2 k1/16), then DFT4 across them.
+template <typename T>
+struct Dft<T, 16> {
+  __device__ __forceinline__ static void run(cx<T>* v, T s) {
+    const T c1 = (T)0.92387953251128675613;  // cos(pi/8)
+    const T s1 = (T)0.38268343236508977173;  // sin(pi/8)
+    const T r = (T)0.70710678118654752440;
+    cx<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cx<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      Dft<T, 4>::run(t, s);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+    }
+    // twiddles w^(n2 k1), w = exp(s 2 pi i/16); exponents 0..9
+    y[1][1] = y[1][1] * mk<T>(c1, s * s1);
+    y[1][2] = y[1][2] * mk<T>(r, s * r);
+    y[1][3] = y[1][3] * mk<T>(s1, s * c1);
+    y[2][1] = y[2][1] * mk<T>(r, s * r);
+    y[2][2] = mul_is(y[2][2], s);
+    y[2][3] = y[2][3] * mk<T>(-r, s * r);
+    y[3][1] = y[3][1] * mk<T>(s1, s * c1);
+    y[3][2] = y[3][2] * mk<T>(-r, s * r);
+    y[3][3] = y[3][3] * mk<T>(-c1, -s * s1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      Dft<T, 4>::run(t, s);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 // ------------------------------------------------------------- LDS Stockham
 constexpr int kMaxPass = 16;
 

@@ -218,16 +218,19 @@ __global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(
   const int bx = t % nbx, by = t / nbx;
   const int x0 = bx * C;
   const bool valid = x0 + c < a.n[0];
-  const long long off = x0 + c + (long long)by * a.n[0] * (gam ? 1 : a.n[1]);
+  // uniform 64-bit tile base + 32-bit per-lane element offsets
   const long long M = a.M;
-  cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M + off;
+  cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M + x0 +
+             (long long)by * a.n[0] * (gam ? 1 : a.n[1]);
+  const unsigned int Mu = (unsigned int)M, su = (unsigned int)a.stride;
+  const unsigned int lane_off = (unsigned int)c + (unsigned int)j * su;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   cx<T> v[D][R];
 #pragma unroll
   for (int cc = 0; cc < D; ++cc)
 #pragma unroll
     for (int i = 0; i < R; ++i)
-      v[cc][i] = valid ? X[cc * M + (long long)(j + TL * i) * a.stride] : mk<T>(0, 0);
+      v[cc][i] = valid ? X[cc * Mu + lane_off + (unsigned int)(TL * i) * su] : mk<T>(0, 0);
   cx<T>* slot = lds + c * LP;
   if (a.mode != 2) {
 #pragma unroll
@@ -279,7 +282,7 @@ __global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(
 #pragma unroll
     for (int cc = 0; cc < D; ++cc)
 #pragma unroll
-      for (int i = 0; i < R; ++i) X[cc * M + (long long)(j + TL * i) * a.stride] = v[cc][i];
+      for (int i = 0; i < R; ++i) X[cc * Mu + lane_off + (unsigned int)(TL * i) * su] = v[cc][i];
   }
 }
 

@@ -59,6 +59,97 @@ struct LocalMapR {
     Ep = reinterpret_cast<T*>(a.Eprev) + rbase;
   }
 
+  // Row-relative form: pointers advanced to the row start (uniform per
+  // workgroup), k the 32-bit position in the row.
+  struct Row {
+    const uint8_t* ph;
+    const double* rho;
+    T* S;
+    T* Tt;
+    T* Ep;
+  };
+  __device__ __forceinline__ Row row(long long r0) const {
+    Row w;
+    w.ph = phase ? phase + r0 : nullptr;
+    w.rho = dens ? dens + r0 : nullptr;
+    w.S = S ? S + r0 : nullptr;
+    w.Tt = Tt ? Tt + r0 : nullptr;
+    w.Ep = Ep + r0;
+    return w;
+  }
+
+  __device__ __forceinline__ T apply(T raw, const Row& w, unsigned int k, Acc& acc) const {
+    const T x = invM * raw;
+    T E, J, out;
+    if (MK == MAP_ACC_EM) {
+      if (w.ph[k]) {
+        const T sv = w.S[k], tv = w.Tt[k];
+        const T s = p1 * x - q2 * sv - q3 * tv;
+        E = inv1w * x + p1kap * s;
+        J = s1 * E;
+        out = z * ((T)2 * p1 * s - x);
+        w.S[k] = -z * ((T)2 * q2 * s - sv);
+        w.Tt[k] = z * ((T)2 * q3 * s - tv);
+      } else {
+        E = inv1w * x;
+        J = E;
+        out = -z * x;
+      }
+    } else if (MK == MAP_ACC_MS) {
+      E = x;
+      if (w.ph[k]) {
+        const T sv = w.S[k];
+        const T s = p1 * x - q2 * sv;
+        J = s1 * E;
+        out = z * (x - (T)2 * p1 * s);
+        w.S[k] = z * (sv - (T)2 * q2 * s);
+      } else {
+        J = E;
+        out = z * x;
+      }
+    } else {
+      T ce, co, cj, cs;
+      if (MK == MAP_LIN_DENS) {
+        const T rho = (T)w.rho[k];
+        const T sig = (T)1 + (s1 - (T)1) * rho;
+        if (kind == K_MS) {
+          ce = (T)1;
+          co = (T)1 - sig / s0;
+          cj = sig;
+          cs = (T)0;
+        } else if (kind == K_EM) {
+          ce = (T)1 / (sig + s0);
+          co = (sig - s0) * ce;
+          cj = sig;
+          cs = (T)0;
+        } else {   // adjoint
+          ce = (T)1;
+          co = (sig - s0) / (sig + s0);
+          cj = (T)0;
+          cs = sig / (sig + s0);
+        }
+      } else {
+        const bool ph = w.ph[k] != 0;
+        ce = ph ? cE[1] : cE[0];
+        co = ph ? cO[1] : cO[0];
+        cj = ph ? cJ[1] : cJ[0];
+        cs = ph ? cS[1] : cS[0];
+      }
+      E = ce * x;
+      J = cj * E;
+      out = co * x + cs * e0c;
+    }
+    acc.Jr += (double)J;
+    acc.e2 += (double)(E * E);
+    acc.eJ += (double)(E * J);
+    if (iter >= 1) {
+      const T dE = E - w.Ep[k];
+      acc.d2 += (double)(dE * dE);
+    }
+    w.Ep[k] = E;
+    return out;
+  }
+
   __device__ __forceinline__ T apply(T raw, long long g, Acc& acc) const {
     const T x = invM * raw;
     T E, J, out;
@@ -176,11 +267,13 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   lm.load(a, solve, comp, cbase * a.M);
   Acc acc;
   if (valid) {
+    const auto wa = lm.row(rowA * N);
+    const auto wb = lm.row(rowB * N);
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const long long k = j + TL * i;
-      const T oa = lm.apply(v[i].x, rowA * N + k, acc);
-      const T ob = lm.apply(v[i].y, rowB * N + k, acc);
+      const unsigned int k = (unsigned int)(j + TL * i);
+      const T oa = lm.apply(v[i].x, wa, k, acc);
+      const T ob = lm.apply(v[i].y, wb, k, acc);
       v[i] = mk<T>(oa, ob);
     }
   }

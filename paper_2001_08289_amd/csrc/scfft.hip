@@ -73,23 +73,23 @@ bool is_p2(int n) { return n >= 16 && n <= 4096 && (n & (n - 1)) == 0; }
 constexpr int kR = 8;
 
 // --- register-resident launches, dispatched over the power-of-two sizes
-template <typename T, int N>
+template <typename T, int N, int RR = kR>
 void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
-  using SH = XPassShape<N, kR>;
-  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, kR>::LP * sizeof(cx<T>),
+  using SH = XPassShape<N, RR>;
+  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
                               (size_t)5 * (SH::NTH / 64) * sizeof(double));
   switch (mk) {
     case MAP_LIN:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_LIN_DENS:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_ACC_EM:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
       break;
     default:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, kR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
       break;
   }
 }
@@ -115,11 +115,11 @@ void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   }
 }
 
-template <typename T, int N, int D, int CW>
+template <typename T, int N, int D, int CW, int RR = kR>
 void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
-  using SH = LineShape<T, N, kR, CW>;
+  using SH = LineShape<T, N, RR, CW>;
   const size_t lds = (size_t)SH::C * SH::LP * sizeof(cx<T>);
-  hipLaunchKernelGGL((line_p2_kernel<T, N, kR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
+  hipLaunchKernelGGL((line_p2_kernel<T, N, RR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
 }
 
 // cw: tile width actually used (one of the instantiated widths).
@@ -162,6 +162,11 @@ int tuned_c(int cmax) {
     case 4096: CALL(4096); break; \
     default: break;              \
   }
+
+// Radix 16 (2048 = 16*8*16, one LDS exchange fewer) measured faster only for
+// the fp64 Gamma pass of 2048^2 grids; everywhere else radix 8 keeps more
+// waves resident.
+int r16_linec_f64_2048() { return LineShape<double, 2048, 16>::C; }
 
 int p2_xlines(int n) {
   int r = 1;
@@ -206,6 +211,7 @@ struct Plan {
   int xlines = 0, xL = 1, xblocks = 0;
   int gC = 1, yC = 1;
   bool p2x = false, p2g = false, p2y = false;   // register-resident passes
+  bool r16x = false, r16g = false, r16y = false; // radix-16 variants (fp64 2048 Gamma pass)
   int mk = MAP_LIN;                              // local map of the current solves
   bool real = false;                             // real-field mode (half spectra)
   int H = 0;                                     // stored x-spectrum length
@@ -295,13 +301,17 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->p2x = is_p2(n[0]) && !std::getenv("SCFFT_NO_P2");
   p->p2g = is_p2(nlast) && !std::getenv("SCFFT_NO_P2") && (d == 2 || nlast <= 1024);
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
+  p->r16x = false;
+  p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && !std::getenv("SCFFT_NO_R16");
+  p->r16y = false;
   if (p->p2x) {
     p->xL = p2_xlines(n[0]);
   } else {
     p->xL = std::max(1, std::min(el / n[0], p->xlines));
   }
   p->xblocks = real ? (p->xlines / 2 + p->xL - 1) / p->xL : (p->xlines + p->xL - 1) / p->xL;
-  p->gC = p->p2g ? tuned_c(p2_linec(nlast, prec))
+  p->gC = p->r16g ? r16_linec_f64_2048()
+        : p->p2g ? tuned_c(p2_linec(nlast, prec))
                  : std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
   p->yC = d == 3 ? (p->p2y ? tuned_c(p2_linec(n[1], prec))
                            : std::min(pow2_floor(std::max(1, el / n[1])), n[0]))
@@ -626,7 +636,9 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     q.fin = d == 2 ? 1 : 0;
     const dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
     rec(6);
-    if (p->p2g) {
+    if (p->r16g) {
+      if constexpr (sizeof(T) == 8) launch_line_p2_cw<T, 2048, 2, 0, 16>(q, grid, st);
+    } else if (p->p2g) {
       if (d == 2) {
 #define C_(N) launch_line_p2<T, N, 2>(q, grid, st)
         SCFFT_P2_SWITCH(nl, C_)

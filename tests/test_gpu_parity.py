@@ -243,3 +243,60 @@ def test_execution_paths_agree(path, scheme, shape, monkeypatch):
         assert _field_err(got, ref) < 2e-6
     finally:
         scfft.release()
+
+
+def test_full_size_2048_one_iteration_matches_oracle():
+    """At the benchmark size the whole field after one accelerated iteration
+    (both FFT passes, Gamma, the H'' local map) matches the oracle."""
+    chi = inputs.square_array(2048)
+    ref = osolver.solve(chi, 100.0, [1, 0], "acc_em", alpha=0.25, beta=4.0, tol=-1, max_iter=1,
+                        stag_window=0, div_factor=0)
+    for precision, bound in (("fp64", 1e-11), ("fp32", 2e-6)):
+        got = scfft.solve(chi, 100.0, (1, 0), "acc_em", precision=precision, tol=-1, max_iter=1,
+                          stag_window=0, div_factor=0, history=False)
+        err = np.abs(got["E"].cpu().numpy() - ref["E"]).max() / np.abs(ref["E"]).max()
+        assert err < bound, (precision, err)
+        assert abs(got["sigma_star"] - ref["sigma_star"]) < bound * abs(ref["sigma_star"])
+
+
+def test_full_size_3d_laminate_closed_form():
+    """256^3 laminate: harmonic mean across the layers, arithmetic mean along
+    them; fp32 runs the fp64 run's iteration count (precision, not truncation)."""
+    chi = inputs.laminate(256, 3, 0.25, axis=2, seed=4)
+    harm, arith = scalars.laminate_means(100.0, 0.25)
+    for scheme, e0, exact, kw in (("acc_em", (0, 0, 1), harm, dict(alpha=0.0625, beta=16.0)),
+                                  ("ms", (1, 0, 0), arith, {})):
+        r64 = scfft.solve(chi, 100.0, e0, scheme, precision="fp64", tol=1e-12, max_iter=500,
+                          fields=False, history=False, **kw)
+        assert r64["status"] == 0
+        assert abs(r64["sigma_star"] - exact) < 1e-10 * abs(exact)
+        r32 = scfft.solve(chi, 100.0, e0, scheme, precision="fp32", tol=-1,
+                          max_iter=r64["iterations"], stag_window=0, div_factor=0, fields=False,
+                          history=False, **kw)
+        assert abs(r32["sigma_star"] - exact) < 2e-6 * abs(exact)
+
+
+def test_full_size_3d_cube_schemes_agree():
+    """256^3 cube array: MS, EM and the accelerated scheme reach one sigma*."""
+    chi = inputs.cube_array(256)
+    est = scfft.estimate_interval(chi, 60)
+    a_u = min(est["alpha"], 1.0 / est["beta"])
+    vals = [scfft.solve(chi, 100.0, (1, 0, 0), s, alpha=a_u, beta=1 / a_u, tol=1e-11, max_iter=400,
+                        fields=False, history=False) for s in ("ms", "em", "acc_em")]
+    assert all(v["status"] == 0 for v in vals)
+    s0 = vals[0]["sigma_star"]
+    assert all(abs(v["sigma_star"] - s0) < 1e-9 * abs(s0) for v in vals)
+    assert vals[2]["iterations"] < vals[0]["iterations"] < vals[1]["iterations"]
+
+
+def test_graph_cache_reuse_and_recapture():
+    """Replayed graphs give identical results across solves and inputs."""
+    a = inputs.random_phase((64, 64), 0.3, seed=1)
+    b = inputs.random_phase((64, 64), 0.3, seed=2)
+    r1 = scfft.solve(a, 10.0, (1, 0), "acc_em", tol=1e-10, max_iter=300)
+    r2 = scfft.solve(b, 10.0, (1, 0), "acc_em", tol=1e-10, max_iter=300)
+    r3 = scfft.solve(a, 10.0, (1, 0), "acc_em", tol=1e-10, max_iter=300)
+    assert r1["iterations"] == r3["iterations"] and r1["sigma_star"] == r3["sigma_star"]
+    ref = osolver.solve(b, 10.0, [1, 0], "acc_em", alpha=0.25, beta=4.0, tol=1e-10, max_iter=300)
+    assert r2["iterations"] == ref["iterations"]
+    assert abs(r2["sigma_star"] - ref["sigma_star"]) < 1e-12 * abs(ref["sigma_star"])

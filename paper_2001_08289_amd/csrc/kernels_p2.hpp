@@ -84,37 +84,30 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_p2_kernel(XArgs
                      a.part + (((long long)solve * a.d + comp) * gridDim.x + blockIdx.x) * 5, tid);
 }
 
-// Lines per workgroup of the strided passes: at most 16 (128-byte row
-// segments in fp32), at most 1024 threads, and the LDS slots within 64 KiB.
-template <typename T, int N, int R, bool PAD>
-struct LineShapeBase {
-  static constexpr int TL = N / R;
-  static constexpr int LP = PAD ? P2Plan<N, R>::LP : N;
-  static constexpr int c1 = 16;
-  static constexpr int c2 = 1024 / TL;
-  static constexpr int c3 = 65536 / (LP * (int)sizeof(cx<T>));
-  static constexpr int C0 = c1 < c2 ? (c1 < c3 ? c1 : c3) : (c2 < c3 ? c2 : c3);
-};
-// CW = 0 picks the default tile; CW > 0 caps the tile width (tuning).
-// The tile is the widest power of two that fits unpadded, capped at 8 lines
-// and 512 threads (the measured optimum on MI355X: 2 columns at 2048^2, 8
-// lines at 256^3); the padded slot layout is used whenever it still fits.
-template <typename T, int N, int R, int CW = 0>
+// Lines per workgroup of the strided passes.  Every line keeps D LDS slots
+// (its D components are transformed together); the tile is the widest power
+// of two (at most 8 lines, 512 threads) whose slots fit the LDS budget,
+// preferring the padded slot layout -- measured optimum on MI355X: 2 columns
+// at 2048^2 (fp32), 8 lines at 256^3.
+constexpr int kLineLdsBudget = 81920;
+
+template <typename T, int N, int R, int D, int CW = 0>
 struct LineShape {
-  using B = LineShapeBase<T, N, R, false>;
-  static constexpr int TL = B::TL;
-  static constexpr int CF = B::C0 >= 8 ? 8 : B::C0 >= 4 ? 4 : B::C0 >= 2 ? 2 : 1;
-  static constexpr int CT = 512 / TL > 0 ? 512 / TL : 1;
+  static constexpr int TL = N / R;
+  static constexpr int PB = P2Plan<N, R>::LP * (int)sizeof(cx<T>) * D;   // padded bytes per line
+  static constexpr int UB = N * (int)sizeof(cx<T>) * D;                  // unpadded
+  static constexpr int CT = 512 / TL > 0 ? (512 / TL > 8 ? 8 : 512 / TL) : 1;
+  static constexpr int CU = kLineLdsBudget / UB;                         // fits unpadded
+  static constexpr int CF = CU >= 8 ? 8 : CU >= 4 ? 4 : CU >= 2 ? 2 : 1;
   static constexpr int CM = CF < CT ? CF : CT;
   static constexpr int CP = (CW > 0 && CW < CM) ? CW : CM;
-  // prefer the padded layout: halve the tile until it fits (fp64 2048: 1 line)
-  static constexpr int PB = P2Plan<N, R>::LP * (int)sizeof(cx<T>);
-  static constexpr int C = (CP * PB <= 65536 || CP == 1) ? CP
-                         : (CP / 2 * PB <= 65536 || CP == 2) ? CP / 2
-                         : (CP / 4 * PB <= 65536 || CP == 4) ? CP / 4 : CP / 8;
-  static constexpr bool PAD = C * PB <= 65536;
+  static constexpr int C = (CP * PB <= kLineLdsBudget || CP == 1) ? CP
+                         : (CP / 2 * PB <= kLineLdsBudget || CP == 2) ? CP / 2
+                         : (CP / 4 * PB <= kLineLdsBudget || CP == 4) ? CP / 4 : CP / 8;
+  static constexpr bool PAD = C * PB <= kLineLdsBudget;
   static constexpr int LP = PAD ? P2Plan<N, R>::LP : N;
   static constexpr int NTH = TL * C;
+  static constexpr int LDS = C * LP * (int)sizeof(cx<T>) * D;
 };
 
 // Symbol vector of eq. J11 on the grid for one mode, compile-time dimension.
@@ -189,8 +182,8 @@ __device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* 
 // hardware deals workgroups round-robin over the 8 XCDs), letting one L2
 // serve the neighbouring row segments of adjacent tiles.
 template <typename T, int N, int R, int D, int CW>
-__global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(GArgs a) {
-  using SH = LineShape<T, N, R, CW>;
+__global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kernel(GArgs a) {
+  using SH = LineShape<T, N, R, D, CW>;
   constexpr int TL = SH::TL, C = SH::C, LP = SH::LP;
   const bool gam = (a.mode == 0);
   const int d = a.d;
@@ -231,13 +224,8 @@ __global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(
 #pragma unroll
     for (int i = 0; i < R; ++i)
       v[cc][i] = valid ? X[cc * Mu + lane_off + (unsigned int)(TL * i) * su] : mk<T>(0, 0);
-  cx<T>* slot = lds + c * LP;
-  if (a.mode != 2) {
-#pragma unroll
-    for (int cc = 0; cc < D; ++cc) {
-      reg_fft<T, N, R, SH::PAD>(v[cc], slot, j, (T)-1, tw);
-    }
-  }
+  cx<T>* slot = lds + c * D * LP;
+  if (a.mode != 2) reg_fft_multi<T, N, R, SH::PAD, D>(v, slot, LP, j, (T)-1, tw);
   if (gam && valid) {
     const SolveCoef& cf = a.coef[solve];
     const T ga = (T)cf.ga, gb = (T)cf.gb, keep = (T)cf.kz_keep;
@@ -272,12 +260,7 @@ __global__ __launch_bounds__((LineShape<T, N, R, CW>::NTH)) void line_p2_kernel(
       }
     }
   }
-  if (a.mode != 1) {
-#pragma unroll
-    for (int cc = 0; cc < D; ++cc) {
-      reg_fft<T, N, R, SH::PAD>(v[cc], slot, j, (T)1, tw);
-    }
-  }
+  if (a.mode != 1) reg_fft_multi<T, N, R, SH::PAD, D>(v, slot, LP, j, (T)1, tw);
   if (valid) {
 #pragma unroll
     for (int cc = 0; cc < D; ++cc)

@@ -118,3 +118,92 @@ __device__ __forceinline__ void reg_fft_nopad(cx<T> (&v)[R], cx<T>* __restrict__
 }
 
 }  // namespace scfft
+
+namespace scfft {
+
+// D lines owned by the same threads, transformed together: each pass computes
+// the twiddles once for all D lines and the D lines share the pass's two
+// barriers.  Line dd uses the LDS slot at slot + dd*sstride.
+template <typename T, int N, int R, int P, int NS, bool PAD, int D>
+struct P2PassM {
+  using PL = P2Plan<N, R>;
+  static constexpr int r = PL::radix(P);
+  static constexpr int NB = R / r;
+  static constexpr int TL = PL::TL;
+  static constexpr bool FIRST = (P == 0);
+  static constexpr bool LAST = (NS * r == N);
+  static constexpr int STEP = N / (NS * r);
+
+  __device__ __forceinline__ static void run(cx<T> (&v)[D][R], cx<T>* __restrict__ slot,
+                                             int sstride, int j, T sign,
+                                             const cx<T>* __restrict__ tw) {
+    cx<T> x[D][NB][r];
+#pragma unroll
+    for (int dd = 0; dd < D; ++dd)
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int q = 0; q < r; ++q) {
+          if (FIRST) {
+            x[dd][u][q] = v[dd][u + q * NB];
+          } else {
+            x[dd][u][q] = slot[dd * sstride + lpad<PAD>(j + u * TL + q * (N / r))];
+          }
+        }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int b = j + u * TL;
+      if (NS > 1) {
+        const int k = b & (NS - 1);
+        cx<T> w1 = tw[k * STEP];
+        if (sign > 0) w1.y = -w1.y;
+        cx<T> wq[r];
+        wq[1] = w1;
+#pragma unroll
+        for (int q = 2; q < r; ++q) wq[q] = (q & 1) ? wq[q - 1] * w1 : wq[q / 2] * wq[q / 2];
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd)
+#pragma unroll
+          for (int q = 1; q < r; ++q) x[dd][u][q] = x[dd][u][q] * wq[q];
+      }
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd) Dft<T, r>::run(x[dd][u], sign);
+    }
+    if (LAST) {
+#pragma unroll
+      for (int dd = 0; dd < D; ++dd)
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+          for (int q = 0; q < r; ++q) v[dd][u + q * NB] = x[dd][u][q];
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int b = j + u * TL;
+        const int k = b & (NS - 1);
+        const int idxd = (b / NS) * NS * r + k;
+#pragma unroll
+        for (int dd = 0; dd < D; ++dd)
+#pragma unroll
+          for (int q = 0; q < r; ++q) slot[dd * sstride + lpad<PAD>(idxd + q * NS)] = x[dd][u][q];
+      }
+      __syncthreads();
+      P2PassM<T, N, R, P + 1, NS * r, PAD, D>::run(v, slot, sstride, j, sign, tw);
+    }
+  }
+};
+
+template <typename T, int N, int R, int P, bool PAD, int D>
+struct P2PassM<T, N, R, P, N, PAD, D> {
+  __device__ __forceinline__ static void run(cx<T> (&)[D][R], cx<T>*, int, int, T, const cx<T>*) {}
+};
+
+template <typename T, int N, int R, bool PAD, int D>
+__device__ __forceinline__ void reg_fft_multi(cx<T> (&v)[D][R], cx<T>* __restrict__ slot,
+                                              int sstride, int j, T sign,
+                                              const cx<T>* __restrict__ tw) {
+  P2PassM<T, N, R, 0, 1, PAD, D>::run(v, slot, sstride, j, sign, tw);
+}
+
+}  // namespace scfft

@@ -117,8 +117,17 @@ void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
 
 template <typename T, int N, int D, int CW, int RR = kR>
 void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
-  using SH = LineShape<T, N, RR, CW>;
-  const size_t lds = (size_t)SH::C * SH::LP * sizeof(cx<T>);
+  using SH = LineShape<T, N, RR, D, CW>;
+  const size_t lds = (size_t)SH::LDS;
+  if (lds > 65536) {
+    // LDS beyond 64 KiB per workgroup (gfx950 has 160 KiB per CU) is opt-in
+    static bool done = false;
+    if (!done) {
+      (void)hipFuncSetAttribute((const void*)line_p2_kernel<T, N, RR, D, CW>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      done = true;
+    }
+  }
   hipLaunchKernelGGL((line_p2_kernel<T, N, RR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
 }
 
@@ -136,8 +145,8 @@ void launch_line_p2(const GArgs& a, dim3 grid, hipStream_t st) {
 
 template <int N>
 int xlines_p2() { return XPassShape<N, kR>::LINES; }
-template <typename T, int N>
-int linec_p2() { return LineShape<T, N, kR>::C; }
+template <typename T, int N, int D>
+int linec_p2() { return LineShape<T, N, kR, D>::C; }
 
 // Tile width of the strided passes: the widest that fits, or a narrower one
 // from SCFFT_LINE_C (a power of two) for tuning.
@@ -166,7 +175,7 @@ int tuned_c(int cmax) {
 // Radix 16 (2048 = 16*8*16, one LDS exchange fewer) measured faster only for
 // the fp64 Gamma pass of 2048^2 grids; everywhere else radix 8 keeps more
 // waves resident.
-int r16_linec_f64_2048() { return LineShape<double, 2048, 16>::C; }
+int r16_linec_f64_2048() { return LineShape<double, 2048, 16, 2>::C; }
 
 int p2_xlines(int n) {
   int r = 1;
@@ -176,16 +185,36 @@ int p2_xlines(int n) {
   return r;
 }
 
-int p2_linec(int n, int prec) {
+int p2_linec(int n, int prec, int D) {
   int r = 1;
   if (prec == SCFFT_FP32) {
-#define C_(N) r = linec_p2<float, N>()
-    SCFFT_P2_SWITCH(n, C_)
+    if (D == 1) {
+#define C_(N) r = linec_p2<float, N, 1>()
+      SCFFT_P2_SWITCH(n, C_)
 #undef C_
+    } else if (D == 2) {
+#define C_(N) r = linec_p2<float, N, 2>()
+      SCFFT_P2_SWITCH(n, C_)
+#undef C_
+    } else {
+#define C_(N) r = linec_p2<float, N, 3>()
+      SCFFT_P2_SWITCH(n, C_)
+#undef C_
+    }
   } else {
-#define C_(N) r = linec_p2<double, N>()
-    SCFFT_P2_SWITCH(n, C_)
+    if (D == 1) {
+#define C_(N) r = linec_p2<double, N, 1>()
+      SCFFT_P2_SWITCH(n, C_)
 #undef C_
+    } else if (D == 2) {
+#define C_(N) r = linec_p2<double, N, 2>()
+      SCFFT_P2_SWITCH(n, C_)
+#undef C_
+    } else {
+#define C_(N) r = linec_p2<double, N, 3>()
+      SCFFT_P2_SWITCH(n, C_)
+#undef C_
+    }
   }
   return r;
 }
@@ -302,7 +331,7 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->p2g = is_p2(nlast) && !std::getenv("SCFFT_NO_P2") && (d == 2 || nlast <= 1024);
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
   p->r16x = false;
-  p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && !std::getenv("SCFFT_NO_R16");
+  p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && std::getenv("SCFFT_R16");
   p->r16y = false;
   if (p->p2x) {
     p->xL = p2_xlines(n[0]);
@@ -311,9 +340,9 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   }
   p->xblocks = real ? (p->xlines / 2 + p->xL - 1) / p->xL : (p->xlines + p->xL - 1) / p->xL;
   p->gC = p->r16g ? r16_linec_f64_2048()
-        : p->p2g ? tuned_c(p2_linec(nlast, prec))
+        : p->p2g ? tuned_c(p2_linec(nlast, prec, d))
                  : std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
-  p->yC = d == 3 ? (p->p2y ? tuned_c(p2_linec(n[1], prec))
+  p->yC = d == 3 ? (p->p2y ? tuned_c(p2_linec(n[1], prec, 1))
                            : std::min(pow2_floor(std::max(1, el / n[1])), n[0]))
                  : 1;
   const size_t field = (size_t)nsolve * d * p->M * p->esz;

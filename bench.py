@@ -70,6 +70,32 @@ def extra_configs(scfft, inputs, torch) -> dict:
     out = {}
     log = lambda *a: print("#", *a, file=sys.stderr, flush=True)   # noqa: E731
 
+    # 64^2 square array, sigma1 = 10, basic scheme, fp64 to 1e-10 (smallest configuration)
+    chi64 = torch.as_tensor(inputs.square_array(64)).cuda()
+    r = scfft.solve(chi64, 10.0, (1.0, 0.0), "ms", precision="fp64", tol=1e-10, max_iter=1000,
+                    check_every=1, fields=False, history=False)
+    ex = float(np.sqrt((1 + 3 * 10.0) / (3 + 10.0)))
+    out["square_64_ms"] = _row(r, rel_err_J47a=abs(r["sigma_star"] - ex) / ex,
+                               workload="64^2 square array, sigma1 = 10, MS, fp64, tol 1e-10")
+    log("64", out["square_64_ms"])
+
+    # the paper's convergence setup: sigma1 = 0, [alpha, beta] = [1/4, 4], sigma* vs eq. J47a
+    chi2k = torch.as_tensor(inputs.square_array(N)).cuda()
+    ex0 = float(np.sqrt(1.0 / 3.0))
+    hist = {}
+    for scheme in ("ms", "acc_ms", "acc_em"):
+        r = scfft.solve(chi2k, 0.0, (1.0, 0.0), scheme, precision="fp64", alpha=0.25, beta=4.0,
+                        tol=-1, max_iter=40, stag_window=0, div_factor=0, fields=False,
+                        history=True)
+        err = np.abs(r["sigma_history"] - ex0) / ex0
+        hist[scheme] = {f"n{k}": float(err[k]) for k in (1, 5, 10, 20, 30, 40)}
+    hist["em"] = "undefined at sigma1 = 0 (sigma0 = sqrt(sigma1) = 0)"
+    out["sigma1_zero_convergence"] = {
+        "workload": "2048^2 square array, sigma1 = 0, fp64, relative error of sigma*_n vs eq. J47a",
+        "rel_err": hist}
+    log("sigma1=0", hist)
+    del chi2k
+
     # 3D cubic array of cubes at ~25% on 256^3, sigma1 = 100, interval by power iteration
     n3 = 256
     chi3 = torch.as_tensor(inputs.cube_array(n3)).cuda()

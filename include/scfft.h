@@ -186,6 +186,14 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
                             scfft_c64* g, scfft_c64* drho, scfft_c64* dsigma1,
                             scfft_result* fwd, scfft_result* adj);
 
+/* Full effective tensor (the anisotropic generalisation noted after
+ * eq. J13): d solves of the same problem with e0 = e_1 .. e_d, run together
+ * as one batch (prob->e0 is ignored).  tensor (host, d*d, row-major) receives
+ * sigma*_{ij} = <J_i> for e0 = e_j; iterations (host, d entries) may be NULL.
+ * Returns the worst status of the d solves. */
+scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_options* opt,
+                                    scfft_c64* tensor, int* iterations);
+
 /* Average device duration (ms, HIP events on opt->stream) of each kernel of
  * one iteration over `iters` iterations of the given solve configuration:
  * ms[0] real-space x pass, ms[1] Gamma pass (last axis), ms[2] forward y pass

@@ -537,8 +537,8 @@ __device__ __forceinline__ void finalize_solve(const FArgs& a, int solve, int ti
   const int d = ctl->d;
   __shared__ double fred[9][16];
   __shared__ double tot[9];
-  // workgroups of fewer than 64 threads (tiny grids) sum on one thread
-  const int nt = nth >= 64 ? nth : 1;
+  // workgroups that are not whole waves (tiny grids) sum on one thread
+  const int nt = (nth >= 64 && nth % 64 == 0) ? nth : 1;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (tid < nt) {
     for (int c = 0; c < d; ++c) {

@@ -1129,6 +1129,55 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   return read_result(p, 0, prob, res, st, ms);
 }
 
+scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_options* opt,
+                                    scfft_c64* tensor, int* iterations) {
+  if (!prob || !opt || !tensor) return SCFFT_ERR_INVALID_ARG;
+  scfft_problem pr = *prob;
+  for (int i = 0; i < 3; ++i) pr.e0[i] = i == 0 ? 1.0 : 0.0;
+  SolveSpec sp{};
+  scfft_status rc = prepare(&pr, opt, cd(prob->sigma1.re, prob->sigma1.im), &sp);
+  if (rc != SCFFT_OK) return rc;
+  if (prob->density && !opt->sigma0_set) sp.s0 = graded_sigma0(opt->scheme, sp.s1);
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
+  const int d = prob->d;
+  Plan* p = nullptr;
+  const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
+  rc = get_plan(d, prob->n, opt->precision, d, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, d, prob->n));
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, opt->max_iter + 1);
+  if (rc != SCFFT_OK) return rc;
+  std::vector<SolveCtl> c(d);
+  std::vector<SolveCoef> cf(d);
+  for (int j = 0; j < d; ++j) {
+    double e0[3] = {0.0, 0.0, 0.0};
+    e0[j] = 1.0;
+    fill_ctl(c[j], *opt, sp.kind, d, e0);
+    fill_coef(cf[j], sp, prob->density != nullptr, d, e0, (double)p->M);
+  }
+  p->mk = map_kind(sp.kind, prob->density != nullptr);
+  SCFFT_HIP(hipMemcpyAsync(p->ctl, c.data(), sizeof(SolveCtl) * d, hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p->coef, cf.data(), sizeof(SolveCoef) * d, hipMemcpyHostToDevice, st));
+  rc = launch_init(p, st);
+  if (rc != SCFFT_OK) return rc;
+  double ms = 0;
+  rc = run_loop({p}, {prob->phase}, {prob->density}, opt->max_iter, opt->check_every, st, &ms);
+  if (rc != SCFFT_OK) return rc;
+  SCFFT_HIP(hipMemcpyAsync(c.data(), p->ctl, sizeof(SolveCtl) * d, hipMemcpyDeviceToHost, st));
+  SCFFT_HIP(hipStreamSynchronize(st));
+  scfft_status worst = SCFFT_OK;
+  for (int j = 0; j < d; ++j) {
+    for (int i = 0; i < d; ++i) {
+      tensor[i * d + j].re = c[j].meanJ[2 * i];
+      tensor[i * d + j].im = c[j].meanJ[2 * i + 1];
+    }
+    if (iterations) iterations[j] = c[j].iter;
+    if (c[j].status < worst) worst = (scfft_status)c[j].status;
+  }
+  return worst;
+}
+
 scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scfft_options* opts,
                                int nsig, const scfft_c64* sigma1s, scfft_result* results) {
   if (nprob <= 0 || nsig <= 0 || nsig > 256 || !probs || !opts || !sigma1s || !results)

@@ -60,7 +60,7 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ("scfft_default_options", "scfft_solve", "scfft_solve_batch", "scfft_estimate_interval",
-           "scfft_gradient", "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
+           "scfft_gradient", "scfft_effective_tensor", "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
            "scfft_status_string", "scfft_release", "scfft_version")
 
 
@@ -81,6 +81,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.scfft_estimate_interval.restype = ctypes.c_int
     lib.scfft_gradient.argtypes = [P, O, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(c64), R, R]
     lib.scfft_gradient.restype = ctypes.c_int
+    lib.scfft_effective_tensor.argtypes = [P, O, ctypes.POINTER(c64), ctypes.POINTER(ctypes.c_int)]
+    lib.scfft_effective_tensor.restype = ctypes.c_int
     lib.scfft_profile_passes.argtypes = [P, O, ctypes.c_int, dp, ctypes.c_int]
     lib.scfft_profile_passes.restype = ctypes.c_int
     lib.scfft_scheme_scalars.argtypes = [ctypes.c_int, c64, ctypes.c_double, ctypes.c_double,
@@ -323,6 +325,23 @@ def gradient(phase=None, sigma1=20.0, e0=(1.0, 0.0, 0.0), *, density=None, preci
         raise ScfftError(rc, "scfft_gradient")
     return {"status": rc, "g": g, "drho": drho, "dsigma1": ds1.value(),
             "forward": _result_dict(fwd, prob.d, E), "adjoint": _result_dict(adj, prob.d)}
+
+
+def effective_tensor(phase=None, sigma1=10.0, scheme="acc_em", *, density=None, precision="fp64",
+                     symbol="rotated", alpha=0.25, beta=4.0, tol=1e-10, max_iter=1000, check_every=16,
+                     stag_window=20, div_factor=1e3, sigma0=None, stream=None) -> dict:
+    """scfft_effective_tensor: the d x d effective conductivity (column j: e0 = e_j)."""
+    prob, keep = make_problem(phase, density, sigma1, (1.0, 0.0, 0.0))
+    opt = make_options(scheme, precision, symbol, alpha, beta, tol, max_iter, check_every,
+                       stag_window, div_factor, sigma0, stream)
+    d = prob.d
+    out = (c64 * (d * d))()
+    its = (ctypes.c_int * d)()
+    rc = _lib.scfft_effective_tensor(ctypes.byref(prob), ctypes.byref(opt), out, its)
+    if rc in (ERR_INVALID_ARG, ERR_SLIT, ERR_DEVICE, ERR_OOM):
+        raise ScfftError(rc, "scfft_effective_tensor")
+    t = np.array([out[k].value() for k in range(d * d)]).reshape(d, d)
+    return {"tensor": t, "iterations": list(its), "status": rc}
 
 
 def profile_passes(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,

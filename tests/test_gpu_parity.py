@@ -300,3 +300,28 @@ def test_graph_cache_reuse_and_recapture():
     ref = osolver.solve(b, 10.0, [1, 0], "acc_em", alpha=0.25, beta=4.0, tol=1e-10, max_iter=300)
     assert r2["iterations"] == ref["iterations"]
     assert abs(r2["sigma_star"] - ref["sigma_star"]) < 1e-12 * abs(ref["sigma_star"])
+
+
+@pytest.mark.parametrize("shape", [(48, 64), (8, 16, 16)])
+def test_effective_tensor_matches_oracle(shape):
+    chi = inputs.random_phase(shape, 0.35, seed=7)
+    d = len(shape)
+    got = scfft.effective_tensor(chi, 5.0 + 1j, "acc_em", alpha=0.02, beta=50.0, tol=1e-12,
+                                 max_iter=3000)
+    for j in range(d):
+        e0 = [0.0] * d
+        e0[j] = 1.0
+        ref = osolver.solve(chi, 5.0 + 1j, e0, "acc_em", alpha=0.02, beta=50.0, tol=1e-12,
+                            max_iter=3000)
+        assert np.abs(got["tensor"][:, j] - ref["mean_J"]).max() < 1e-10
+
+
+def test_keller_tensor_relation_on_device():
+    """2D Keller interchange, sigma*(1/s) = R sigma*(s)^{-1} R^T, for a random map."""
+    chi = inputs.random_phase((64, 64), 0.4, seed=8)
+    a = scfft.effective_tensor(chi, 7.0, "acc_em", alpha=0.02, beta=50.0, tol=1e-13,
+                               max_iter=3000)["tensor"]
+    b = scfft.effective_tensor(chi, 1 / 7.0, "acc_em", alpha=0.02, beta=50.0, tol=1e-13,
+                               max_iter=3000)["tensor"]
+    rot = np.array([[0.0, -1.0], [1.0, 0.0]])
+    assert np.abs(b - rot @ np.linalg.inv(a) @ rot.T).max() < 1e-10

@@ -72,10 +72,11 @@ struct XArgs {
   const void* tw;       // twiddles for n0
   FftDesc fd;
   long long M;          // voxels per field
-  long long Mh;         // stored elements of one component of X (real mode: (n0/2+1) n1 n2)
+  long long Mh;         // stored elements of one component of X (real mode: H n1 n2)
   int n0, nlines, lines_per_block, d;
   double invM;
   int ignore_done;
+  int packed;           // real mode, 2D: rows of n0/2 values, column 0 = X(0) + i X(n0/2)
 };
 
 // Reduction inputs of the stop rules (see finalize_solve).
@@ -103,6 +104,9 @@ struct GArgs {
   int ignore_done;
   int mode;             // 0: Gamma pass; 1: forward FFT only; 2: inverse FFT only
   int fin;              // 1: workgroup (0,0) of each solve also runs finalize_solve
+  int lmap;             // register passes: 0 column index fastest in the workgroup, 1 line index fastest
+  int cpad;             // register passes: extra LDS elements between the slots of adjacent columns
+  int packed;           // 2D real mode: column 0 holds kx = 0 (real part) and kx = n0/2 (imaginary)
   FArgs f;
 };
 

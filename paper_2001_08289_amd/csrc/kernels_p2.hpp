@@ -173,6 +173,33 @@ __device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* 
   }
 }
 
+// Gamma_1 step of eq. J11 (J44-J45 in H'') at one Fourier mode m for the D
+// components w: at k = 0 the scheme's source term, elsewhere
+// w <- ga w + gb n (n . w) / |n|^2 with the symbol vector n of the mode.
+template <typename T, int D>
+__device__ __forceinline__ void gamma_mode(const GArgs& a, const SolveCoef& cf, T ga, T gb, T keep,
+                                           const int* m, cx<T>* w) {
+  const bool zero = (m[0] == 0) && (m[1] == 0) && (D == 2 || m[2] == 0);
+  if (zero) {
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) w[cc] = keep * w[cc] + ld2<T>(cf.kz_src[cc]);
+    return;
+  }
+  cx<T> nv[3];
+  const T nrm = mode_symbol_d<T, D>(a, m, nv);
+  cx<T> dot = mk<T>(0, 0);
+  if (a.symbol == SYM_NETWORK) {
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) dot = dot + conj(nv[cc]) * w[cc];
+  } else {
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) dot = dot + nv[cc] * w[cc];
+  }
+  const T inv = (T)1 / nrm;
+#pragma unroll
+  for (int cc = 0; cc < D; ++cc) w[cc] = ga * w[cc] + gb * (inv * (nv[cc] * dot));
+}
+
 // Strided passes: a tile of C lines adjacent along x, thread (j, c) with c
 // fastest so that each row of the tile is one contiguous segment.
 //   mode 0: forward FFT, Gamma_1 (eq. J11 / J44-J45) with the scheme's k = 0
@@ -195,14 +222,18 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
-  // the first pass after the x pass also reduces its partials and applies
-  // the stop rules (one workgroup per solve, overlapped with the FFT tiles)
-  if (a.fin && blockIdx.x == 0 && blockIdx.y == 0 && comp0 == 0)
-    finalize_solve(a.f, solve, tid, SH::NTH);
-  const int c = tid % C;
-  const int j = tid / C;
+  // The first pass after the x pass also reduces its partials and applies
+  // the stop rules: the grid then has one extra column of workgroups, and the
+  // one at y = 0 of each solve does only that, beside the FFT tiles rather
+  // than in front of one of them.
+  const int nbx = gridDim.x - (a.fin ? 1 : 0), nby = gridDim.y;
+  if (a.fin && (int)blockIdx.x == nbx) {
+    if (blockIdx.y == 0 && comp0 == 0) finalize_solve(a.f, solve, tid, SH::NTH);
+    return;
+  }
+  const int c = a.lmap ? tid / TL : tid % C;
+  const int j = a.lmap ? tid - c * TL : tid / C;
   // XCD-aware tile order
-  const int nbx = gridDim.x, nby = gridDim.y;
   const int nb = nbx * nby;
   const int b = blockIdx.y * nbx + blockIdx.x;
   int t = b;
@@ -224,8 +255,23 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
 #pragma unroll
     for (int i = 0; i < R; ++i)
       v[cc][i] = valid ? X[cc * Mu + lane_off + (unsigned int)(TL * i) * su] : mk<T>(0, 0);
-  cx<T>* slot = lds + c * D * LP;
+  cx<T>* slot = lds + c * (D * LP + a.cpad);
   if (a.mode != 2) reg_fft_multi<T, N, R, SH::PAD, D>(v, slot, LP, j, (T)-1, tw);
+  // 2D real mode: column 0 of tile 0 carries kx = 0 in its real and
+  // kx = n0/2 in its imaginary part, both real along y, so after the y-FFT
+  //   Z(k) = A(k) + i B(k),  A = (Z(k) + conj Z(-k)) / 2,  B = (Z(k) - conj Z(-k)) / 2i;
+  // the mirrored values come through the column's LDS slot.
+  const bool pk = gam && a.packed && x0 == 0;   // uniform over the workgroup
+  if (pk) {
+    __syncthreads();   // the forward FFT's last LDS reads are done
+    if (c == 0) {
+#pragma unroll
+      for (int cc = 0; cc < D; ++cc)
+#pragma unroll
+        for (int i = 0; i < R; ++i) slot[cc * LP + lpad<SH::PAD>(j + TL * i)] = v[cc][i];
+    }
+    __syncthreads();
+  }
   if (gam && valid) {
     const SolveCoef& cf = a.coef[solve];
     const T ga = (T)cf.ga, gb = (T)cf.gb, keep = (T)cf.kz_keep;
@@ -239,24 +285,29 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
         m[1] = by;
         m[2] = j + TL * i;
       }
-      const bool zero = (m[0] == 0) && (m[1] == 0) && (D == 2 || m[2] == 0);
-      if (zero) {
+      cx<T> w[D];
 #pragma unroll
-        for (int cc = 0; cc < D; ++cc) v[cc][i] = keep * v[cc][i] + ld2<T>(cf.kz_src[cc]);
-      } else {
-        cx<T> nv[3];
-        const T nrm = mode_symbol_d<T, D>(a, m, nv);
-        cx<T> dot = mk<T>(0, 0);
-        if (a.symbol == SYM_NETWORK) {
+      for (int cc = 0; cc < D; ++cc) w[cc] = v[cc][i];
+      // (a branch per mode keeps the registers of one mode live at a time)
+      if (D == 2 && pk && c == 0) {
+        const int km = (N - (j + TL * i)) & (N - 1);
+        cx<T> b[D];
 #pragma unroll
-          for (int cc = 0; cc < D; ++cc) dot = dot + conj(nv[cc]) * v[cc][i];
-        } else {
-#pragma unroll
-          for (int cc = 0; cc < D; ++cc) dot = dot + nv[cc] * v[cc][i];
+        for (int cc = 0; cc < D; ++cc) {
+          const cx<T> zm = conj(slot[cc * LP + lpad<SH::PAD>(km)]);
+          const cx<T> s = w[cc] + zm, df = w[cc] - zm;
+          w[cc] = mk<T>((T)0.5 * s.x, (T)0.5 * s.y);
+          b[cc] = mk<T>((T)0.5 * df.y, (T)-0.5 * df.x);
         }
-        const T inv = (T)1 / nrm;
+        const int mn[3] = {a.n[0], m[1], 0};   // kx = n0/2 (= the column count)
+        gamma_mode<T, D>(a, cf, ga, gb, keep, m, w);
+        gamma_mode<T, D>(a, cf, ga, gb, keep, mn, b);
 #pragma unroll
-        for (int cc = 0; cc < D; ++cc) v[cc][i] = ga * v[cc][i] + gb * (inv * (nv[cc] * dot));
+        for (int cc = 0; cc < D; ++cc) v[cc][i] = mk<T>(w[cc].x - b[cc].y, w[cc].y + b[cc].x);
+      } else {
+        gamma_mode<T, D>(a, cf, ga, gb, keep, m, w);
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) v[cc][i] = w[cc];
       }
     }
   }

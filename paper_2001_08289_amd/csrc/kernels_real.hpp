@@ -9,10 +9,13 @@
 // the same algebra as the complex form of eq. J36 / J44.
 //
 // Layout: real-space arrays (E_prev, S', T') are real [b][c][N^d]; the iterate
-// X is stored as the Hermitian half of its x-direction spectrum,
-// kx = 0..n0/2, rows of H = n0/2 + 1 complex values ([b][c][H n1 n2]).
-// Two real rows of one component share one complex FFT of length n0:
-// w = a + i b, and a, b are recovered from w(k) and w(n0 - k).
+// X is stored as the Hermitian half of its x-direction spectrum, kx = 0..n0/2.
+// In 3D a row holds H = n0/2 + 1 complex values ([b][c][H n1 n2]).  In 2D the
+// two coefficients that are real for a real row, kx = 0 and kx = n0/2, share
+// column 0 (real and imaginary part), so a row holds H = n0/2 values: the
+// Gamma pass then has n0/2 columns, which tile the machine without a lone
+// last tile.  Two real rows of one component share one complex FFT of length
+// n0: w = a + i b, and a, b are recovered from w(k) and w(n0 - k).
 #pragma once
 
 #include "kernels_p2.hpp"
@@ -229,7 +232,7 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   using SH = XPassShape<N, R>;
   constexpr int TL = SH::TL, LINES = SH::LINES, NTH = SH::NTH;
   constexpr int LP = P2Plan<N, R>::LP;
-  constexpr int H = N / 2 + 1;
+  const int H = a.packed ? N / 2 : N / 2 + 1;
   const int solve = blockIdx.z;
   const int comp = blockIdx.y;
   if (!a.ignore_done && a.ctl[solve].done) return;
@@ -251,7 +254,11 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
     const int k = j + TL * i;
     cx<T> av = mk<T>(0, 0), bv = mk<T>(0, 0);
     if (valid) {
-      if (k <= N / 2) {
+      if (a.packed && (k == 0 || k == N / 2)) {
+        const cx<T> pa = XA[0], pb = XB[0];
+        av = mk<T>(k == 0 ? pa.x : pa.y, (T)0);
+        bv = mk<T>(k == 0 ? pb.x : pb.y, (T)0);
+      } else if (k <= N / 2) {
         av = XA[k];
         bv = XB[k];
       } else {
@@ -284,14 +291,28 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   for (int i = 0; i < R; ++i) slot[lpad<true>(j + TL * i)] = v[i];
   __syncthreads();
   if (valid) {
+    T a0 = 0, b0 = 0;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int k = j + TL * i;
       if (k <= N / 2) {
         const cx<T> wn = conj(slot[lpad<true>((N - k) & (N - 1))]);
         const cx<T> s = v[i] + wn, dd = v[i] - wn;
-        XA[k] = mk<T>((T)0.5 * s.x, (T)0.5 * s.y);
-        XB[k] = mk<T>((T)0.5 * dd.y, (T)-0.5 * dd.x);
+        const cx<T> xa = mk<T>((T)0.5 * s.x, (T)0.5 * s.y);
+        const cx<T> xb = mk<T>((T)0.5 * dd.y, (T)-0.5 * dd.x);
+        if (a.packed && (k == 0 || k == N / 2)) {
+          // thread j = 0 holds both k = 0 (i = 0) and k = N/2 (i = R/2)
+          if (k == 0) {
+            a0 = xa.x;
+            b0 = xb.x;
+          } else {
+            XA[0] = mk<T>(a0, xa.x);
+            XB[0] = mk<T>(b0, xb.x);
+          }
+        } else {
+          XA[k] = xa;
+          XB[k] = xb;
+        }
       }
     }
   }

@@ -118,14 +118,14 @@ void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
 template <typename T, int N, int D, int CW, int RR = kR>
 void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
   using SH = LineShape<T, N, RR, D, CW>;
-  const size_t lds = (size_t)SH::LDS;
+  const size_t lds = (size_t)SH::LDS + (size_t)SH::C * a.cpad * sizeof(cx<T>);
   if (lds > 65536) {
     // LDS beyond 64 KiB per workgroup (gfx950 has 160 KiB per CU) is opt-in
-    static bool done = false;
-    if (!done) {
+    static size_t set = 0;
+    if (lds > set) {
       (void)hipFuncSetAttribute((const void*)line_p2_kernel<T, N, RR, D, CW>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      done = true;
+      set = lds;
     }
   }
   hipLaunchKernelGGL((line_p2_kernel<T, N, RR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
@@ -143,6 +143,21 @@ void launch_line_p2(const GArgs& a, dim3 grid, hipStream_t st) {
   }
 }
 
+// 2D real mode: pack kx = 0 and kx = n0/2 into one column when that lowers
+// the number of Gamma-pass workgroups the busiest CU runs (the packed tile
+// does a little more work, so packing only pays where it removes a tile
+// from some CU).
+bool pack_pays(int n0, int c, int nsolve, int dev) {
+  if (const char* e = std::getenv("SCFFT_PACK")) return std::atoi(e) != 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    return false;
+  const long long tu = (long long)nsolve * ((n0 / 2 + 1 + c - 1) / c);
+  const long long tp = (long long)nsolve * ((n0 / 2 + c - 1) / c);
+  return (tu + cus - 1) / cus > (tp + cus - 1) / cus;
+}
+
 template <int N>
 int xlines_p2() { return XPassShape<N, kR>::LINES; }
 template <typename T, int N, int D>
@@ -150,6 +165,11 @@ int linec_p2() { return LineShape<T, N, kR, D>::C; }
 
 // Tile width of the strided passes: the widest that fits, or a narrower one
 // from SCFFT_LINE_C (a power of two) for tuning.
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
 int tuned_c(int cmax) {
   const char* e = std::getenv("SCFFT_LINE_C");
   if (!e) return cmax;
@@ -243,6 +263,7 @@ struct Plan {
   bool r16x = false, r16g = false, r16y = false; // radix-16 variants (fp64 2048 Gamma pass)
   int mk = MAP_LIN;                              // local map of the current solves
   bool real = false;                             // real-field mode (half spectra)
+  bool packed = false;                           // 2D real mode: kx = 0 and n0/2 share column 0
   int H = 0;                                     // stored x-spectrum length
   long long Mh = 0;                              // stored elements per component of X
 };
@@ -322,13 +343,12 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->M = (long long)n[0] * n[1] * n2;
   p->esz = prec == SCFFT_FP32 ? 8 : 16;
   p->real = real;
-  p->H = real ? n[0] / 2 + 1 : n[0];
-  p->Mh = (long long)p->H * n[1] * n2;
   const int el = elems_for(prec);
   const int nlast = n[d - 1];
   p->xlines = (int)(p->M / n[0]);
   p->p2x = is_p2(n[0]) && !std::getenv("SCFFT_NO_P2");
   p->p2g = is_p2(nlast) && !std::getenv("SCFFT_NO_P2") && (d == 2 || nlast <= 1024);
+  p->H = real ? n[0] / 2 + 1 : n[0];
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
   p->r16x = false;
   p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && std::getenv("SCFFT_R16");
@@ -345,6 +365,11 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->yC = d == 3 ? (p->p2y ? tuned_c(p2_linec(n[1], prec, 1))
                            : std::min(pow2_floor(std::max(1, el / n[1])), n[0]))
                  : 1;
+  // the packed column is unpacked by the register Gamma pass (2D)
+  p->packed = real && d == 2 && p->p2g && !std::getenv("SCFFT_NO_PACK") &&
+              (p->r16g || pack_pays(n[0], p->gC, nsolve, dev));
+  if (p->packed) p->H = n[0] / 2;
+  p->Mh = (long long)p->H * n[1] * n2;
   const size_t field = (size_t)nsolve * d * p->M * p->esz;
   // real mode: X holds half spectra, the real-space arrays hold real values
   const size_t xfield = real ? (size_t)nsolve * d * p->Mh * p->esz : field;
@@ -589,6 +614,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     a.d = d;
     a.invM = 1.0 / (double)p->M;
     a.ignore_done = ignore_done;
+    a.packed = p->packed ? 1 : 0;
     // the x pass reuses its LDS for a 5 x (kNT/64) fp64 reduction
     rec(0);
     if (p->real) {
@@ -633,6 +659,9 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
   g.ignore_done = ignore_done;
   g.f = f;
   g.fin = 0;
+  g.packed = p->packed ? 1 : 0;
+  g.lmap = env_int("SCFFT_LMAP", 0);
+  g.cpad = env_int("SCFFT_CPAD", 0);
   for (int a = 0; a < d; ++a) g.symtab[a] = p->sym[a];
   if (d == 3) {
     GArgs y = g;
@@ -642,9 +671,10 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     y.stride = p->H;
     y.mode = 1;
     y.fin = 1;   // first pass after the x pass
-    const dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
+    dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(4);
     if (p->p2y) {
+      grid.x += 1;   // the finalizing workgroups
 #define C_(N) launch_line_p2<T, N, 1>(y, grid, st)
       SCFFT_P2_SWITCH(p->n[1], C_)
 #undef C_
@@ -663,7 +693,8 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     q.stride = d == 2 ? p->H : p->H * p->n[1];
     q.mode = 0;
     q.fin = d == 2 ? 1 : 0;
-    const dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
+    dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
+    if ((p->r16g || p->p2g) && q.fin) grid.x += 1;   // the finalizing workgroups
     rec(6);
     if (p->r16g) {
       if constexpr (sizeof(T) == 8) launch_line_p2_cw<T, 2048, 2, 0, 16>(q, grid, st);

@@ -31,6 +31,10 @@ SIGMAS = (10.0, 100.0, 1000.0, 0.01)
 SCHEMES = ("ms", "em", "acc_em")
 HEADLINE = dict(scheme="acc_em", precision="fp32", sigma1=100.0)
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+PROFILE_SUMMARY = "xpass_gamma_2048sq_acc_em_fp32.txt"
+KERNEL_NAMES = {"xpass": "void scfft::xpass_r2c_kernel<float, 2048,",
+                "gamma": "void scfft::line_p2_kernel<float, 2048,"}
 
 
 def algorithmic_bytes(scheme: str, precision: str, d: int, frac1: float, n0: int,
@@ -232,14 +236,13 @@ def main() -> int:
 
     hs = HEADLINE
     if args.profile_only:
-        # calibration for the HBM byte counters: a 256 MiB fill, then a
-        # 256 MiB read + 256 MiB write copy
+        # calibration for the HBM byte counters: a 256 MiB fill (writes
+        # only), then a 256 MiB sum (reads only)
         cal_x = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         cal_x.fill_(1.0)
-        cal_y = torch.empty_like(cal_x)
-        cal_y.copy_(cal_x)
+        float(cal_x.sum())
         torch.cuda.synchronize()
-        del cal_x, cal_y
+        del cal_x
         prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
                                     alpha=0.25, beta=4.0, iters=args.profile_iters)
         print(json.dumps({"profile": prof, "config": hs, "grid": [N, N]}), flush=True)
@@ -271,9 +274,14 @@ def main() -> int:
     dominant = max(("xpass", "gamma"), key=lambda k: prof[k])
     achieved = ab[dominant] * N * N / (prof[dominant] * 1e-3) / 1e9
     iter_bytes = (ab["xpass"] + ab["gamma"]) * N * N
+    # measured HBM bytes per launch of the dominant kernel (rocprofv3 FETCH_SIZE +
+    # WRITE_SIZE, calibrated), if the committed summary matches these kernels
+    from paper_2001_08289_amd.profile_summary import read_traffic
+    traffic = read_traffic(os.path.join(HERE, "profiles", PROFILE_SUMMARY),
+                           KERNEL_NAMES[dominant])
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": traffic,
                 "bytes_per_launch": ab[dominant] * N * N,
                 "per_kernel": kern,
                 "iteration_GBps": round(iter_bytes / (ms_per_step * 1e-3) / 1e9, 1)}

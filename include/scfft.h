@@ -203,6 +203,39 @@ scfft_status scfft_profile_passes(const scfft_problem* prob,
                                   const scfft_options* opt, int iters,
                                   double* ms, int cap);
 
+/* Coefficients of the expansion of eqs. J5 / J7,
+ *   sigma* / sqrt(t) = sum_{n >= 0} c_n z^n,  t of eq. J6,  z = (sqrt t - 1)/(sqrt t + 1),
+ * for a two-phase map (prob->phase required, prob->density must be NULL;
+ * prob->sigma1 is ignored: the c_n depend on the geometry, e0 and the
+ * interval only).  In H'' the Eyre-Milton operator is z K with
+ * K = 2 p p^T - I at phase-1 voxels and -1 on Q elsewhere (p of eq. J24), so
+ * the fixed point expands in u_0 = (e0, 0, 0), u_k = W'' K u_{k-1} (W'' of
+ * eq. J44) and c_0 = 1, c_k = 2 <(K u_{k-1})_Q> . e0 / |e0|^2: the accelerated
+ * iteration's kernels run nterms times with z = 1 and no source term.
+ * Uses opt->alpha, opt->beta (0 < alpha < beta), opt->precision,
+ * opt->symbol, opt->stream; the stop rules are off.  coeffs (host) receives
+ * c_0 .. c_nterms (nterms + 1 entries), 1 <= nterms <= 100000.
+ * Rounding excites the zero-weight modes whose singularities (sigma1 = 0
+ * and infinity) map to |z| = min(|z(t(0))|, |z(t(inf))|) < 1, so the
+ * coefficients carry noise growing like that radius^-n: sums and Pade
+ * approximants are reliable where |z| stays below it. */
+scfft_status scfft_series_coefficients(const scfft_problem* prob,
+                                       const scfft_options* opt, int nterms,
+                                       scfft_c64* coeffs);
+
+/* sigma*(sigma1) from the coefficients of scfft_series_coefficients, for
+ * nsig values sigma1s (host arrays; out receives nsig values):
+ * pade_m = 0: the partial sum sqrt(t) sum_{n <= nterms} c_n z^n;
+ * pade_m > 0: sqrt(t) a(z)/q(z), the [L/M] Pade approximant with
+ * M = pade_m, L = nterms - M (q_0 = 1; q solves the M linear conditions
+ * sum_{j <= M} q_j c_{L+i-j} = 0, i = 1..M, by LU with partial pivoting).
+ * Host fp64 only.  SCFFT_ERR_SLIT if a sigma1 lies on [-beta, -alpha];
+ * SCFFT_ERR_INVALID_ARG for a singular Pade system or bad sizes. */
+scfft_status scfft_series_evaluate(int nterms, const scfft_c64* coeffs,
+                                   double alpha, double beta, int pade_m,
+                                   int nsig, const scfft_c64* sigma1s,
+                                   scfft_c64* out);
+
 /* Scheme scalars (host fp64, no device use): out[] receives, as complex
  * numbers, sigma0, t (eq. J23; 0 for MS/EM), z (the expansion variable of
  * eqs. J1, J2, J42a or J4), p1, p2, p3 (eq. J24; 0 for MS/EM), E2' (eq. J21),

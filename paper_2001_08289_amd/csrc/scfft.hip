@@ -1209,6 +1209,129 @@ scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_optio
   return worst;
 }
 
+scfft_status scfft_series_coefficients(const scfft_problem* prob, const scfft_options* opt,
+                                       int nterms, scfft_c64* coeffs) {
+  if (!prob || !opt || !coeffs || nterms < 1 || nterms > 100000) return SCFFT_ERR_INVALID_ARG;
+  if (!prob->phase || prob->density) return SCFFT_ERR_INVALID_ARG;
+  scfft_options o = *opt;
+  o.scheme = SCFFT_ACC_EM;
+  o.tol = -1.0;
+  o.max_iter = nterms;
+  o.stag_window = 0;
+  o.div_factor = 0.0;
+  SolveSpec sp{};
+  // sigma1 = 1 gives t = 1; only p (from alpha, beta) enters the operator K
+  scfft_status rc = prepare(prob, &o, cd(1.0, 0.0), &sp);
+  if (rc != SCFFT_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
+  Plan* p = nullptr;
+  rc = get_plan(prob->d, prob->n, o.precision, 1, true, o.symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n));
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, nterms + 1);
+  if (rc != SCFFT_OK) return rc;
+  SolveCtl c;
+  SolveCoef cf;
+  fill_ctl(c, o, sp.kind, prob->d, prob->e0);
+  fill_coef(cf, sp, false, prob->d, prob->e0, (double)p->M);
+  // z = 1 and no source: the local map returns K x, and with s1 = 1,
+  // inv1w = -1, p1kap = 2 p1 its "physical field" E = -x + 2 p1 s (phase 1),
+  // -x (phase 2) is (K x)_Q, so the reduced <J> = <E> is <(K u)_Q>
+  put(cf.s1, cd(1.0, 0.0));
+  put(cf.z, cd(1.0, 0.0));
+  put(cf.inv1w, cd(-1.0, 0.0));
+  put(cf.p1kap, 2.0 * sp.sc.p[0]);
+  for (int i = 0; i < prob->d; ++i) {
+    put(cf.kz_src[i], cd(0.0, 0.0));
+    put(cf.init_src[i], cd((double)p->M * prob->e0[i], 0.0));
+  }
+  p->mk = map_kind(sp.kind, false);
+  SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  rc = launch_init(p, st);
+  if (rc != SCFFT_OK) return rc;
+  double ms = 0;
+  rc = run_loop({p}, {prob->phase}, {nullptr}, nterms, o.check_every, st, &ms);
+  if (rc != SCFFT_OK) return rc;
+  std::vector<double> hs(2 * (size_t)nterms);
+  SCFFT_HIP(hipMemcpyAsync(hs.data(), p->hist_s, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+  SCFFT_HIP(hipMemcpyAsync(&c, p->ctl, sizeof(c), hipMemcpyDeviceToHost, st));
+  SCFFT_HIP(hipStreamSynchronize(st));
+  // iteration n reduces <(K u_n)_Q>; a non-finite stop leaves later entries unset
+  const int valid = c.status == SCFFT_ERR_DIVERGED ? std::min(c.iter, nterms) : nterms;
+  coeffs[0] = scfft_c64{1.0, 0.0};
+  for (int k = 1; k <= nterms; ++k) {
+    if (k - 1 < valid) {
+      coeffs[k] = scfft_c64{2.0 * hs[2 * (k - 1)], 2.0 * hs[2 * (k - 1) + 1]};
+    } else {
+      coeffs[k] = scfft_c64{NAN, NAN};
+    }
+  }
+  return SCFFT_OK;
+}
+
+scfft_status scfft_series_evaluate(int nterms, const scfft_c64* coeffs, double alpha, double beta,
+                                   int pade_m, int nsig, const scfft_c64* sigma1s,
+                                   scfft_c64* out) {
+  if (nterms < 0 || nterms > 100000 || !coeffs || nsig < 0 || pade_m < 0 || pade_m > nterms)
+    return SCFFT_ERR_INVALID_ARG;
+  if (nsig > 0 && (!sigma1s || !out)) return SCFFT_ERR_INVALID_ARG;
+  if (!(alpha > 0.0) || !(beta > alpha) || !std::isfinite(beta)) return SCFFT_ERR_INVALID_ARG;
+  std::vector<cd> c(nterms + 1);
+  for (int k = 0; k <= nterms; ++k) c[k] = cd(coeffs[k].re, coeffs[k].im);
+  auto cc = [&](int i) { return (i >= 0 && i <= nterms) ? c[i] : cd(0.0, 0.0); };
+  const int M = pade_m, L = nterms - pade_m;
+  std::vector<cd> q(M + 1, cd(0.0, 0.0)), a(L + 1, cd(0.0, 0.0));
+  q[0] = 1.0;
+  if (M > 0) {
+    // sum_{j=1..M} q_j c_{L+i-j} = -c_{L+i}, i = 1..M: LU with partial pivoting
+    std::vector<cd> A((size_t)M * M), b(M);
+    for (int i = 0; i < M; ++i) {
+      for (int j = 0; j < M; ++j) A[(size_t)i * M + j] = cc(L + (i + 1) - (j + 1));
+      b[i] = -cc(L + i + 1);
+    }
+    for (int k = 0; k < M; ++k) {
+      int piv = k;
+      for (int i = k + 1; i < M; ++i)
+        if (std::abs(A[(size_t)i * M + k]) > std::abs(A[(size_t)piv * M + k])) piv = i;
+      if (!(std::abs(A[(size_t)piv * M + k]) > 0.0)) return SCFFT_ERR_INVALID_ARG;
+      if (piv != k) {
+        for (int j = 0; j < M; ++j) std::swap(A[(size_t)k * M + j], A[(size_t)piv * M + j]);
+        std::swap(b[k], b[piv]);
+      }
+      for (int i = k + 1; i < M; ++i) {
+        const cd f = A[(size_t)i * M + k] / A[(size_t)k * M + k];
+        for (int j = k; j < M; ++j) A[(size_t)i * M + j] -= f * A[(size_t)k * M + j];
+        b[i] -= f * b[k];
+      }
+    }
+    for (int k = M - 1; k >= 0; --k) {
+      cd v = b[k];
+      for (int j = k + 1; j < M; ++j) v -= A[(size_t)k * M + j] * q[j + 1];
+      q[k + 1] = v / A[(size_t)k * M + k];
+    }
+  }
+  for (int i = 0; i <= L; ++i) {
+    cd v(0.0, 0.0);
+    for (int j = 0; j <= std::min(i, M); ++j) v += q[j] * c[i - j];
+    a[i] = v;
+  }
+  for (int n = 0; n < nsig; ++n) {
+    const cd s(sigma1s[n].re, sigma1s[n].im);
+    if (s.imag() == 0.0 && s.real() >= -beta && s.real() <= -alpha) return SCFFT_ERR_SLIT;
+    const cd t = (s + alpha) * (1.0 + beta) / ((s + beta) * (1.0 + alpha));   // eq. J6
+    const cd w = std::sqrt(t);
+    const cd z = (w - 1.0) / (w + 1.0);                                      // eq. J7
+    cd num(0.0, 0.0), den(0.0, 0.0);
+    for (int i = L; i >= 0; --i) num = num * z + a[i];
+    for (int j = M; j >= 0; --j) den = den * z + q[j];
+    const cd v = w * num / den;
+    out[n] = scfft_c64{v.real(), v.imag()};
+  }
+  return SCFFT_OK;
+}
+
 scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scfft_options* opts,
                                int nsig, const scfft_c64* sigma1s, scfft_result* results) {
   if (nprob <= 0 || nsig <= 0 || nsig > 256 || !probs || !opts || !sigma1s || !results)

@@ -60,7 +60,8 @@ class Result(ctypes.Structure):
 
 
 EXPORTS = ("scfft_default_options", "scfft_solve", "scfft_solve_batch", "scfft_estimate_interval",
-           "scfft_gradient", "scfft_effective_tensor", "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
+           "scfft_gradient", "scfft_effective_tensor", "scfft_series_coefficients",
+           "scfft_series_evaluate", "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
            "scfft_status_string", "scfft_release", "scfft_version")
 
 
@@ -83,6 +84,12 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.scfft_gradient.restype = ctypes.c_int
     lib.scfft_effective_tensor.argtypes = [P, O, ctypes.POINTER(c64), ctypes.POINTER(ctypes.c_int)]
     lib.scfft_effective_tensor.restype = ctypes.c_int
+    lib.scfft_series_coefficients.argtypes = [P, O, ctypes.c_int, ctypes.POINTER(c64)]
+    lib.scfft_series_coefficients.restype = ctypes.c_int
+    lib.scfft_series_evaluate.argtypes = [ctypes.c_int, ctypes.POINTER(c64), ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(c64), ctypes.POINTER(c64)]
+    lib.scfft_series_evaluate.restype = ctypes.c_int
     lib.scfft_profile_passes.argtypes = [P, O, ctypes.c_int, dp, ctypes.c_int]
     lib.scfft_profile_passes.restype = ctypes.c_int
     lib.scfft_scheme_scalars.argtypes = [ctypes.c_int, c64, ctypes.c_double, ctypes.c_double,
@@ -342,6 +349,34 @@ def effective_tensor(phase=None, sigma1=10.0, scheme="acc_em", *, density=None, 
         raise ScfftError(rc, "scfft_effective_tensor")
     t = np.array([out[k].value() for k in range(d * d)]).reshape(d, d)
     return {"tensor": t, "iterations": list(its), "status": rc}
+
+
+def series_coefficients(phase, e0=(1.0, 0.0, 0.0), *, alpha=0.25, beta=4.0, nterms=40,
+                        precision="fp64", symbol="rotated", check_every=16, stream=None) -> np.ndarray:
+    """scfft_series_coefficients: c_0 .. c_nterms of sigma*/sqrt(t) = sum c_n z^n."""
+    prob, keep = make_problem(phase, None, 1.0, e0)
+    opt = make_options("acc_em", precision, symbol, alpha, beta, check_every=check_every,
+                       stream=stream)
+    out = (c64 * (nterms + 1))()
+    rc = _lib.scfft_series_coefficients(ctypes.byref(prob), ctypes.byref(opt), int(nterms), out)
+    if rc != OK:
+        raise ScfftError(rc, "scfft_series_coefficients")
+    return np.array([out[k].value() for k in range(nterms + 1)])
+
+
+def series_evaluate(coeffs, sigma1s, *, alpha=0.25, beta=4.0, pade_m=0) -> np.ndarray:
+    """scfft_series_evaluate: sigma*(sigma1) from the coefficients (partial sum, or
+    the [L/M] Pade approximant with M = pade_m)."""
+    c = np.asarray(coeffs, dtype=np.complex128).ravel()
+    s = np.atleast_1d(np.asarray(sigma1s, dtype=np.complex128)).ravel()
+    cin = (c64 * len(c))(*[c64(float(v.real), float(v.imag)) for v in c])
+    sin = (c64 * len(s))(*[c64(float(v.real), float(v.imag)) for v in s])
+    out = (c64 * max(1, len(s)))()
+    rc = _lib.scfft_series_evaluate(len(c) - 1, cin, float(alpha), float(beta), int(pade_m),
+                                    len(s), sin, out)
+    if rc != OK:
+        raise ScfftError(rc, "scfft_series_evaluate")
+    return np.array([out[k].value() for k in range(len(s))])
 
 
 def profile_passes(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,

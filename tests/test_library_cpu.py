@@ -151,3 +151,31 @@ def test_status_strings():
     for s in range(-7, 1):
         assert scfft.status_string(s) and scfft.status_string(s) != "unknown status"
     assert scfft.status_string(42) == "unknown status"
+
+
+def test_series_evaluate_matches_oracle_partial_sums_and_pade():
+    """Host-side series / Pade evaluation (no device use) against the oracle."""
+    from oracle import series as oseries
+    rng = np.random.default_rng(3)
+    c = (rng.standard_normal(21) + 0.3j * rng.standard_normal(21)) * 0.5 ** np.arange(21)
+    c[0] = 1.0
+    s1 = np.array([10.0, 3 + 2j, 0.05, -0.1 + 0.4j, 250.0])
+    for m in (0, 4, 10):
+        got = scfft.series_evaluate(c, s1, alpha=0.25, beta=4.0, pade_m=m)
+        if m == 0:
+            ref = oseries.evaluate(c, s1, 0.25, 4.0)
+        else:
+            a, q = oseries.pade(c, m)
+            ref = oseries.evaluate_pade(a, q, s1, 0.25, 4.0)
+        assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_series_evaluate_rejects_slit_and_bad_sizes():
+    c = np.array([1.0, 0.1, 0.01])
+    with pytest.raises(scfft.ScfftError) as e:
+        scfft.series_evaluate(c, [-1.0], alpha=0.25, beta=4.0)
+    assert e.value.status == scfft.ERR_SLIT
+    with pytest.raises(scfft.ScfftError):
+        scfft.series_evaluate(c, [1.0], alpha=0.25, beta=4.0, pade_m=3)
+    with pytest.raises(scfft.ScfftError):
+        scfft.series_evaluate(c, [1.0], alpha=4.0, beta=0.25)

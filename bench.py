@@ -98,6 +98,41 @@ def extra_configs(scfft, inputs, torch) -> dict:
         "workload": "2048^2 square array, sigma1 = 0, fp64, relative error of sigma*_n vs eq. J47a",
         "rel_err": hist}
     log("sigma1=0", hist)
+
+    # series coefficients of eqs. J5-J7 from one run, sigma* for many sigma1
+    a_, b_ = 0.25, 4.0
+    s_real = np.logspace(-3, 4, 2048)
+    zc = 0.3 * np.exp(2j * np.pi * (np.arange(2048) + 0.5) / 2048)
+    s_cplx = np.array([complex(scfft.sigma1_from_z(a_, b_, z)) for z in zc])
+    s_all = np.concatenate([s_real, s_cplx])
+    ser = {"workload": "2048^2 square array, e0 = e1, [alpha, beta] = [1/4, 4]: c_0..c_40 from one "
+                       "run, then sigma* at 4096 sigma1 (2048 on [1e-3, 1e4], 2048 on |z| = 0.3)"}
+    for prec in ("fp64", "fp32"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = scfft.series_coefficients(chi2k, (1.0, 0.0), alpha=a_, beta=b_, nterms=40,
+                                      precision=prec)
+        t_run = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        vals = scfft.series_evaluate(c, s_all, alpha=a_, beta=b_)
+        pade = scfft.series_evaluate(c[:25], s_all, alpha=a_, beta=b_, pade_m=12)
+        t_eval = time.perf_counter() - t0
+        exact = np.sqrt((1 + 3 * s_all) / (3 + s_all))       # eq. J47a (principal branch)
+        direct = {}
+        for s in SIGMAS:
+            r = scfft.solve(chi2k, s, (1.0, 0.0), "acc_em", precision=prec, alpha=a_, beta=b_,
+                            tol=1e-12 if prec == "fp64" else 1e-6, max_iter=500, fields=False,
+                            history=False)
+            v = scfft.series_evaluate(c, [s], alpha=a_, beta=b_)[0]
+            direct[str(s)] = {"series_vs_solve": float(abs(v - r["sigma_star"]) / abs(r["sigma_star"])),
+                              "solve_ms": round(r["elapsed_ms"], 3), "solve_iters": r["iterations"]}
+        ser[prec] = {"coeff_run_ms": round(1e3 * t_run, 3), "eval_ms_4096": round(1e3 * t_eval, 3),
+                     "sigma1_per_s": len(s_all) / (t_run + t_eval),
+                     "max_rel_err_vs_J47a": float(np.max(np.abs(vals - exact) / np.abs(exact))),
+                     "pade_12_12_max_rel_err_vs_J47a": float(np.max(np.abs(pade - exact) / np.abs(exact))),
+                     "direct": direct}
+        log("series", prec, ser[prec])
+    out["series_2048"] = ser
     del chi2k
 
     # 3D cubic array of cubes at ~25% on 256^3, sigma1 = 100, interval by power iteration

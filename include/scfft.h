@@ -171,6 +171,40 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters,
                                      double* beta, double* mu_min,
                                      double* mu_max);
 
+/* Lanczos process for the spectral measure behind the singularities of
+ * sigma*(sigma1) (section "Estimating the parameters alpha and beta": the
+ * singularities sit at sigma1 = 1 - 1/mu, mu in the support of the measure
+ * of A = Gamma_1 chi Gamma_1 on E with respect to v_0 = Gamma_1 chi e0).
+ * fp64 on the device: the unnormalised recurrence
+ *   w_0 = v_0,  w_j = A w_{j-1} - a_{j-1} w_{j-1} - gamma_{j-1} w_{j-2},
+ *   a_j = (w_j, chi w_j)/(w_j, w_j),  gamma_j = |w_j|^2/|w_{j-1}|^2,
+ * one x pass and one Gamma pass per step, without reorthogonalisation.
+ * prob->phase and prob->e0 (non-zero) are used; 1 <= steps <= 200.
+ * a (host, steps entries) receives a_0..a_{m-1}, b (host, steps entries)
+ * receives b_j = sqrt(gamma_j), j = 1..m-1, in b[0..m-2]; norm0 = |v_0|^2
+ * (sum over voxels); m = number of steps completed (fewer than steps when the
+ * Krylov space closes, i.e. |w_j| vanishes).  The Gauss rule of the
+ * tridiagonal matrix (a, b) gives the nodes mu_i and weights
+ * norm0 * (first eigenvector component)^2. */
+scfft_status scfft_lanczos(const scfft_problem* prob, int steps, int symbol,
+                           void* stream, double* a, double* b, double* norm0,
+                           int* m);
+
+/* Interval [alpha, beta] from the Lanczos Gauss rule (host Jacobi
+ * eigen-decomposition of the tridiagonal matrix): mu_min / mu_max are the
+ * extreme nodes whose weight exceeds rel_weight times the total (spurious
+ * nodes excited by rounding carry negligible weight), alpha = 1/mu_max - 1,
+ * beta = 1/mu_min - 1, and the interval for the accelerated scheme follows
+ * the floating-point stability rule alpha_used = min(alpha, 1/beta),
+ * beta_used = 1/alpha_used (every output pointer may be NULL).
+ * SCFFT_ERR_INVALID_ARG when no node lies inside (0, 1). */
+scfft_status scfft_estimate_interval_lanczos(const scfft_problem* prob, int steps,
+                                             int symbol, void* stream,
+                                             double rel_weight, double* alpha,
+                                             double* beta, double* alpha_used,
+                                             double* beta_used, double* mu_min,
+                                             double* mu_max);
+
 /* Gradient of sigma* by an adjoint solve.  Forward: SCFFT_EM (sigma0 =
  * sqrt(sigma_min sigma_max) over the medium unless opt->sigma0_set).
  * Adjoint: the transposed Eyre-Milton iteration m <- Z W m + c with

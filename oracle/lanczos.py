@@ -67,7 +67,7 @@ def gauss_rule(a, b, n0: float = 1.0):
     return theta, n0 * vec[0] ** 2
 
 
-def support_estimate(a, b, n0: float = 1.0, rel_weight: float = 1e-10):
+def support_estimate(a, b, n0: float = 1.0, rel_weight: float = 1e-8):
     """(mu_min, mu_max): extreme Gauss nodes whose weight exceeds
     rel_weight times the total weight."""
     theta, wts = gauss_rule(a, b, n0)
@@ -75,7 +75,7 @@ def support_estimate(a, b, n0: float = 1.0, rel_weight: float = 1e-10):
     return float(theta[keep].min()), float(theta[keep].max())
 
 
-def interval(chi, e0=(1.0, 0.0, 0.0), steps: int = 60, symbol="rotated", rel_weight: float = 1e-10):
+def interval(chi, e0=(1.0, 0.0, 0.0), steps: int = 60, symbol="rotated", rel_weight: float = 1e-8):
     """(alpha, beta, alpha_u, beta_u, mu_min, mu_max)."""
     a, b, n0 = lanczos(chi, e0, steps, symbol)
     mu_min, mu_max = support_estimate(a, b, n0, rel_weight)

@@ -28,6 +28,7 @@ struct LocalMapR {
   T cE[2], cO[2], cJ[2], cS[2];
   T s1, s0, p1, q2, q3, z, inv1w, p1kap;
   T invM, e0c;
+  T la, lg;   // Lanczos: a_{j-1}, gamma_{j-1}
   const uint8_t* phase;
   const double* dens;
   T* S;
@@ -55,6 +56,8 @@ struct LocalMapR {
     p1kap = (T)cf.p1kap[0];
     invM = (T)a.invM;
     e0c = (T)ctl.e0[comp];
+    la = (T)ctl.lz_a;
+    lg = (T)ctl.lz_g;
     phase = a.phase;
     dens = a.density;
     S = a.Sslot ? reinterpret_cast<T*>(a.Sslot) + rbase : nullptr;
@@ -81,9 +84,29 @@ struct LocalMapR {
     return w;
   }
 
+  // Lanczos step (see LocalMap): S holds w_{j-2}, E_prev w_{j-1}
+  __device__ __forceinline__ T lanczos(T x, bool ph, T& sref, T& eref, Acc& acc) const {
+    T v = x;
+    if (iter == 0) {
+      sref = (T)0;
+      eref = (T)0;
+    } else {
+      const T w1 = eref, w2 = sref;
+      v = x - la * w1 - lg * w2;
+      sref = w1;
+      eref = v;
+    }
+    const T cw = ph ? v : (T)0;
+    acc.Jr += (double)cw;
+    acc.e2 += (double)(v * v);
+    acc.eJ += (double)(cw * cw);
+    return cw;
+  }
+
   __device__ __forceinline__ T apply(T raw, const Row& w, unsigned int k, Acc& acc) const {
     const T x = invM * raw;
     T E, J, out;
+    if (MK == MAP_LANCZOS) return lanczos(x, w.ph[k] != 0, w.S[k], w.Ep[k], acc);
     if (MK == MAP_ACC_EM) {
       if (w.ph[k]) {
         const T sv = w.S[k], tv = w.Tt[k];
@@ -156,6 +179,7 @@ struct LocalMapR {
   __device__ __forceinline__ T apply(T raw, long long g, Acc& acc) const {
     const T x = invM * raw;
     T E, J, out;
+    if (MK == MAP_LANCZOS) return lanczos(x, phase[g] != 0, S[g], Ep[g], acc);
     if (MK == MAP_ACC_EM) {
       if (phase[g]) {
         const T sv = S[g], tv = Tt[g];

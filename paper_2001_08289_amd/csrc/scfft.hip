@@ -88,6 +88,10 @@ void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
     case MAP_ACC_EM:
       hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
       break;
+    case MAP_LANCZOS:   // fp64 only
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
+      break;
     default:
       hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
       break;
@@ -108,6 +112,10 @@ void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
       break;
     case MAP_ACC_EM:
       hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
+      break;
+    case MAP_LANCZOS:   // fp64 only
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
       break;
     default:
       hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
@@ -269,6 +277,7 @@ struct Plan {
 };
 
 int map_kind(int kind, bool density) {
+  if (kind == K_LANCZOS) return MAP_LANCZOS;
   if (kind == K_ACC_EM) return MAP_ACC_EM;
   if (kind == K_ACC_MS) return MAP_ACC_MS;
   return density ? MAP_LIN_DENS : MAP_LIN;
@@ -523,6 +532,12 @@ void fill_coef(SolveCoef& c, const SolveSpec& sp, bool density, int d, const dou
       c.ga = 1;
       c.gb = -2;
       c.kz_keep = 1;
+      break;
+    case K_LANCZOS:   // pure Gamma_1 projection, start field e0
+      c.ga = 0;
+      c.gb = 1;
+      c.kz_keep = 0;
+      init = 1.0;
       break;
     case K_POWER: {
       for (int ph = 0; ph < 2; ++ph) {
@@ -1450,6 +1465,159 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
   if (mu_min) *mu_min = mmin;
   if (alpha) *alpha = 1.0 / mmax - 1.0;
   if (beta) *beta = 1.0 / mmin - 1.0;
+  return SCFFT_OK;
+}
+
+// Lanczos process on Gamma_1 chi Gamma_1 from v_0 = Gamma_1 chi e0 (fp64):
+// the unnormalised three-term recurrence w_j = A w_{j-1} - a_{j-1} w_{j-1}
+// - gamma_{j-1} w_{j-2} runs in the iteration kernels (one x pass and one
+// Gamma pass per step); a_j = (w_j, chi w_j)/(w_j, w_j) (= (w_j, A w_j)/(w_j, w_j)
+// since w_j lies in E), b_j = |w_j|/|w_{j-1}|.  No reorthogonalisation: the
+// extreme Gauss nodes converge first, later copies carry negligible weight.
+scfft_status lanczos_run(const scfft_problem* prob, int steps, int symbol, hipStream_t st,
+                         std::vector<double>& a, std::vector<double>& b, double* norm0) {
+  if (!prob || !prob->phase || prob->density || steps < 1 || steps > 200 || symbol < 0 ||
+      symbol > 2 || bad_e0(prob))
+    return SCFFT_ERR_INVALID_ARG;
+  scfft_status rc = check_dims(prob->d, prob->n, SCFFT_FP64);
+  if (rc != SCFFT_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_mutex);
+  Plan* p = nullptr;
+  SolveSpec lz{};
+  lz.kind = K_LANCZOS;
+  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 1, true, symbol, st, &p, 0,
+                real_ok(lz, prob->d, prob->n));
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, steps + 2);
+  if (rc != SCFFT_OK) return rc;
+  scfft_options o;
+  scfft_default_options(&o);
+  o.tol = -1.0;
+  o.max_iter = steps;
+  o.stag_window = 0;
+  o.div_factor = 0.0;
+  SolveCtl c;
+  SolveCoef cf;
+  fill_ctl(c, o, K_LANCZOS, prob->d, prob->e0);
+  fill_coef(cf, lz, false, prob->d, prob->e0, (double)p->M);
+  p->mk = MAP_LANCZOS;
+  SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  rc = launch_init(p, st);
+  if (rc != SCFFT_OK) return rc;
+  double ms = 0;
+  rc = run_loop({p}, {prob->phase}, {nullptr}, steps, 32, st, &ms);
+  if (rc != SCFFT_OK) return rc;
+  std::vector<double> hs(2 * (size_t)(steps + 1));
+  SCFFT_HIP(hipMemcpyAsync(hs.data(), p->hist_s, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+  SCFFT_HIP(hipMemcpyAsync(&c, p->ctl, sizeof(c), hipMemcpyDeviceToHost, st));
+  SCFFT_HIP(hipStreamSynchronize(st));
+  // iterate n >= 1 holds (a_{n-1}, |w_{n-1}|^2); a breakdown at n invalidates n
+  const int last = c.status == SCFFT_ERR_DIVERGED ? c.iter - 1 : std::min(c.iter, steps);
+  a.clear();
+  b.clear();
+  for (int n = 1; n <= last; ++n) {
+    a.push_back(hs[2 * n]);
+    if (n >= 2) b.push_back(std::sqrt(hs[2 * n + 1] / hs[2 * (n - 1) + 1]));
+  }
+  if (a.empty()) return SCFFT_ERR_INVALID_ARG;   // v_0 = 0: e0 sees no inhomogeneity
+  if (norm0) *norm0 = hs[3];
+  return SCFFT_OK;
+}
+
+// Gauss rule of the symmetric tridiagonal matrix (a, b): eigenvalues and
+// squared first eigenvector components (cyclic Jacobi rotations on the
+// dense matrix; m <= 200).
+void gauss_rule(const std::vector<double>& a, const std::vector<double>& b, std::vector<double>& node,
+                std::vector<double>& w0) {
+  const int m = (int)a.size();
+  std::vector<double> A((size_t)m * m, 0.0), V((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    A[(size_t)i * m + i] = a[i];
+    V[(size_t)i * m + i] = 1.0;
+    if (i + 1 < m) A[(size_t)i * m + i + 1] = A[(size_t)(i + 1) * m + i] = b[i];
+  }
+  double scale = 0;
+  for (double v : A) scale += v * v;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < m; ++i)
+      for (int j = i + 1; j < m; ++j) off += A[(size_t)i * m + j] * A[(size_t)i * m + j];
+    if (off <= 1e-32 * scale) break;
+    for (int pp = 0; pp < m; ++pp)
+      for (int q = pp + 1; q < m; ++q) {
+        const double apq = A[(size_t)pp * m + q];
+        if (apq == 0.0) continue;
+        const double th = (A[(size_t)q * m + q] - A[(size_t)pp * m + pp]) / (2.0 * apq);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < m; ++k) {   // columns pp, q
+          const double akp = A[(size_t)k * m + pp], akq = A[(size_t)k * m + q];
+          A[(size_t)k * m + pp] = cs * akp - sn * akq;
+          A[(size_t)k * m + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < m; ++k) {   // rows pp, q
+          const double apk = A[(size_t)pp * m + k], aqk = A[(size_t)q * m + k];
+          A[(size_t)pp * m + k] = cs * apk - sn * aqk;
+          A[(size_t)q * m + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < m; ++k) {
+          const double vkp = V[(size_t)k * m + pp], vkq = V[(size_t)k * m + q];
+          V[(size_t)k * m + pp] = cs * vkp - sn * vkq;
+          V[(size_t)k * m + q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+  node.resize(m);
+  w0.resize(m);
+  for (int i = 0; i < m; ++i) {
+    node[i] = A[(size_t)i * m + i];
+    w0[i] = V[i] * V[i];   // first row of V: first components of the eigenvectors
+  }
+}
+
+scfft_status scfft_lanczos(const scfft_problem* prob, int steps, int symbol, void* stream,
+                           double* a, double* b, double* norm0, int* m) {
+  if (!a || !b || !m) return SCFFT_ERR_INVALID_ARG;
+  std::vector<double> va, vb;
+  scfft_status rc = lanczos_run(prob, steps, symbol, reinterpret_cast<hipStream_t>(stream), va, vb,
+                                norm0);
+  if (rc != SCFFT_OK) return rc;
+  *m = (int)va.size();
+  for (size_t i = 0; i < va.size(); ++i) a[i] = va[i];
+  for (size_t i = 0; i < vb.size(); ++i) b[i] = vb[i];
+  return SCFFT_OK;
+}
+
+scfft_status scfft_estimate_interval_lanczos(const scfft_problem* prob, int steps, int symbol,
+                                             void* stream, double rel_weight, double* alpha,
+                                             double* beta, double* alpha_used, double* beta_used,
+                                             double* mu_min, double* mu_max) {
+  if (!(rel_weight >= 0.0) || !(rel_weight < 1.0)) return SCFFT_ERR_INVALID_ARG;
+  std::vector<double> va, vb, node, w0;
+  double n0 = 0;
+  scfft_status rc = lanczos_run(prob, steps, symbol, reinterpret_cast<hipStream_t>(stream), va, vb,
+                                &n0);
+  if (rc != SCFFT_OK) return rc;
+  gauss_rule(va, vb, node, w0);
+  double tot = 0;
+  for (double w : w0) tot += w;
+  double lo = INFINITY, hi = -INFINITY;
+  for (size_t i = 0; i < node.size(); ++i)
+    if (w0[i] > rel_weight * tot) {
+      lo = std::min(lo, node[i]);
+      hi = std::max(hi, node[i]);
+    }
+  if (!(lo > 0.0) || !(hi < 1.0) || !(lo <= hi)) return SCFFT_ERR_INVALID_ARG;
+  const double al = 1.0 / hi - 1.0, be = 1.0 / lo - 1.0;
+  // floating-point stability of the accelerated scheme: alpha beta = 1
+  const double au = std::min(al, 1.0 / be);
+  if (mu_min) *mu_min = lo;
+  if (mu_max) *mu_max = hi;
+  if (alpha) *alpha = al;
+  if (beta) *beta = be;
+  if (alpha_used) *alpha_used = au;
+  if (beta_used) *beta_used = 1.0 / au;
   return SCFFT_OK;
 }
 

@@ -61,7 +61,8 @@ class Result(ctypes.Structure):
 
 EXPORTS = ("scfft_default_options", "scfft_solve", "scfft_solve_batch", "scfft_estimate_interval",
            "scfft_gradient", "scfft_effective_tensor", "scfft_series_coefficients",
-           "scfft_series_evaluate", "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
+           "scfft_series_evaluate", "scfft_lanczos", "scfft_estimate_interval_lanczos",
+           "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
            "scfft_status_string", "scfft_release", "scfft_version")
 
 
@@ -90,6 +91,12 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
                                           ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                           ctypes.POINTER(c64), ctypes.POINTER(c64)]
     lib.scfft_series_evaluate.restype = ctypes.c_int
+    lib.scfft_lanczos.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, dp, dp, dp,
+                                  ctypes.POINTER(ctypes.c_int)]
+    lib.scfft_lanczos.restype = ctypes.c_int
+    lib.scfft_estimate_interval_lanczos.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                                    ctypes.c_double, dp, dp, dp, dp, dp, dp]
+    lib.scfft_estimate_interval_lanczos.restype = ctypes.c_int
     lib.scfft_profile_passes.argtypes = [P, O, ctypes.c_int, dp, ctypes.c_int]
     lib.scfft_profile_passes.restype = ctypes.c_int
     lib.scfft_scheme_scalars.argtypes = [ctypes.c_int, c64, ctypes.c_double, ctypes.c_double,
@@ -377,6 +384,34 @@ def series_evaluate(coeffs, sigma1s, *, alpha=0.25, beta=4.0, pade_m=0) -> np.nd
     if rc != OK:
         raise ScfftError(rc, "scfft_series_evaluate")
     return np.array([out[k].value() for k in range(len(s))])
+
+
+def lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="rotated", stream=None) -> dict:
+    """scfft_lanczos: recurrence coefficients a, b and |v_0|^2 (fp64)."""
+    prob, keep = make_problem(phase, None, 1.0, e0)
+    a = (ctypes.c_double * steps)()
+    b = (ctypes.c_double * steps)()
+    n0 = ctypes.c_double()
+    m = ctypes.c_int()
+    rc = _lib.scfft_lanczos(ctypes.byref(prob), int(steps), SYMBOLS[symbol], _stream_ptr(stream), a,
+                            b, ctypes.byref(n0), ctypes.byref(m))
+    if rc != OK:
+        raise ScfftError(rc, "scfft_lanczos")
+    return {"a": np.array(a[:m.value]), "b": np.array(b[:max(0, m.value - 1)]), "norm0": n0.value}
+
+
+def estimate_interval_lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="rotated",
+                              rel_weight=1e-8, stream=None) -> dict:
+    """scfft_estimate_interval_lanczos: raw and stability-symmetrised interval."""
+    prob, keep = make_problem(phase, None, 1.0, e0)
+    v = [ctypes.c_double() for _ in range(6)]
+    rc = _lib.scfft_estimate_interval_lanczos(ctypes.byref(prob), int(steps), SYMBOLS[symbol],
+                                              _stream_ptr(stream), float(rel_weight),
+                                              *[ctypes.byref(x) for x in v])
+    if rc != OK:
+        raise ScfftError(rc, "scfft_estimate_interval_lanczos")
+    keys = ("alpha", "beta", "alpha_used", "beta_used", "mu_min", "mu_max")
+    return {k: x.value for k, x in zip(keys, v)}
 
 
 def profile_passes(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,

@@ -99,6 +99,14 @@ def extra_configs(scfft, inputs, torch) -> dict:
         "rel_err": hist}
     log("sigma1=0", hist)
 
+    # Lanczos support estimate of the square array at 2048^2 (fp64, 60 steps)
+    t0 = time.perf_counter()
+    lz = scfft.estimate_interval_lanczos(chi2k, (1.0, 0.0), steps=60)
+    out["lanczos_2048"] = {"interval": lz, "time_ms": round(1e3 * (time.perf_counter() - t0), 3),
+                           "workload": "2048^2 square array, e0 = e1, 60 Lanczos steps (fp64); "
+                                       "continuum support [1/4, 3/4]"}
+    log("lanczos 2048", out["lanczos_2048"])
+
     # series coefficients of eqs. J5-J7 from one run, sigma* for many sigma1
     a_, b_ = 0.25, 4.0
     s_real = np.logspace(-3, 4, 2048)
@@ -153,8 +161,18 @@ def extra_configs(scfft, inputs, torch) -> dict:
                              voxel_iters_per_s=n3 ** 3 * r["iterations"] / (r["elapsed_ms"] * 1e-3)
                              if r["elapsed_ms"] > 0 else None))
             log("3d", rows[-1])
+    # Lanczos support estimate (60 fp64 steps) and an accelerated solve with its interval
+    t0 = time.perf_counter()
+    lz = scfft.estimate_interval_lanczos(chi3, (1.0, 0.0, 0.0), steps=60)
+    t_lz = time.perf_counter() - t0
+    r = scfft.solve(chi3, 100.0, (1.0, 0.0, 0.0), "acc_em", precision="fp32",
+                    alpha=lz["alpha_used"], beta=lz["beta_used"], tol=1e-6, max_iter=2000,
+                    check_every=8, fields=False, history=False, raise_on_error=False)
+    lz_row = {"interval": lz, "estimate_s": round(t_lz, 3),
+              "acc_em_fp32": _row(r, tol=1e-6)}
+    log("3d lanczos", lz_row)
     out["cube_256"] = {"interval_raw": est, "interval_used": [a_u, b_u],
-                       "estimate_s": round(t_est, 3), "runs": rows,
+                       "estimate_s": round(t_est, 3), "runs": rows, "lanczos": lz_row,
                        "workload": "3D cubic array of cubes (side 161 of 256, f = 0.24875), "
                                    "sigma1 = 100, e0 = e1"}
     del chi3

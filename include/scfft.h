@@ -192,8 +192,10 @@ scfft_status scfft_lanczos(const scfft_problem* prob, int steps, int symbol,
 
 /* Interval [alpha, beta] from the Lanczos Gauss rule (host Jacobi
  * eigen-decomposition of the tridiagonal matrix): mu_min / mu_max are the
- * extreme nodes whose weight exceeds rel_weight times the total (spurious
- * nodes excited by rounding carry negligible weight), alpha = 1/mu_max - 1,
+ * extreme nodes whose weight exceeds rel_weight times the total and which
+ * pass the Cullum-Willoughby test (a simple node that is also an eigenvalue
+ * of the matrix without its first row and column, within 1e-8, comes from
+ * rounding and is dropped), alpha = 1/mu_max - 1,
  * beta = 1/mu_min - 1, and the interval for the accelerated scheme follows
  * the floating-point stability rule alpha_used = min(alpha, 1/beta),
  * beta_used = 1/alpha_used (every output pointer may be NULL).

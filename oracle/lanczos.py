@@ -19,8 +19,9 @@ The eigenvalues theta_i of the tridiagonal matrix T (diagonal a, off-diagonal
 b) are the Gauss nodes of the measure; the squared first components of its
 eigenvectors, times |v_0|^2, are the Gauss weights.  Then
     alpha = 1/mu_max - 1,   beta = 1/mu_min - 1
-from the extreme nodes whose weight is not negligible, and the interval
-actually used follows the floating-point stability rule of the accelerated
+from the extreme nodes whose weight is not negligible and which pass the
+Cullum-Willoughby test for spurious nodes (needed by a recurrence without
+reorthogonalisation; harmless here), and the interval actually used follows the floating-point stability rule of the accelerated
 scheme: alpha_u = min(alpha, 1/beta), beta_u = 1/alpha_u.
 """
 from __future__ import annotations
@@ -67,15 +68,32 @@ def gauss_rule(a, b, n0: float = 1.0):
     return theta, n0 * vec[0] ** 2
 
 
-def support_estimate(a, b, n0: float = 1.0, rel_weight: float = 1e-8):
-    """(mu_min, mu_max): extreme Gauss nodes whose weight exceeds
-    rel_weight times the total weight."""
+def spurious(a, b, tol: float = 1e-8):
+    """Cullum-Willoughby test: a simple eigenvalue of T that is also an
+    eigenvalue of T with its first row and column removed (within tol) does
+    not belong to the measure of v_0 (it is produced by rounding once the
+    Lanczos vectors lose orthogonality); numerically multiple eigenvalues
+    are copies of converged ones and are kept."""
+    theta, _ = gauss_rule(a, b)
+    if len(a) < 2:
+        return np.zeros(len(theta), dtype=bool)
+    that = np.linalg.eigvalsh(np.diag(a[1:]) + np.diag(b[1:], 1) + np.diag(b[1:], -1))
+    out = np.zeros(len(theta), dtype=bool)
+    for i, t in enumerate(theta):
+        multiple = np.sum(np.abs(theta - t) < 1e-8) >= 2
+        out[i] = (not multiple) and np.min(np.abs(that - t)) < tol
+    return out
+
+
+def support_estimate(a, b, n0: float = 1.0, rel_weight: float = 1e-6):
+    """(mu_min, mu_max): extreme Gauss nodes that pass the Cullum-Willoughby
+    test and whose weight exceeds rel_weight times the total weight."""
     theta, wts = gauss_rule(a, b, n0)
-    keep = wts > rel_weight * wts.sum()
+    keep = (wts > rel_weight * wts.sum()) & ~spurious(a, b)
     return float(theta[keep].min()), float(theta[keep].max())
 
 
-def interval(chi, e0=(1.0, 0.0, 0.0), steps: int = 60, symbol="rotated", rel_weight: float = 1e-8):
+def interval(chi, e0=(1.0, 0.0, 0.0), steps: int = 60, symbol="rotated", rel_weight: float = 1e-6):
     """(alpha, beta, alpha_u, beta_u, mu_min, mu_max)."""
     a, b, n0 = lanczos(chi, e0, steps, symbol)
     mu_min, mu_max = support_estimate(a, b, n0, rel_weight)

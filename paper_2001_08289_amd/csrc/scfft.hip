@@ -70,10 +70,22 @@ int pow2_floor(int v) {
 
 bool is_p2(int n) { return n >= 16 && n <= 4096 && (n & (n - 1)) == 0; }
 
-constexpr int kR = 8;
+
+// Register FFT radix per pass (measured on MI355X, fp32 and fp64): radix 4
+// (twice the threads per line, more waves in flight) wins for the x pass up
+// to n0 = 1024 (fp64: 2048) and for the 2D Gamma pass up to 1024; radix 8
+// (fewer LDS exchanges) wins for longer lines and for the 3D strided passes.
+template <typename T, int N>
+constexpr int xpass_radix() {
+  return (N <= 1024 || (sizeof(T) == 8 && N <= 2048)) ? 4 : 8;
+}
+template <typename T, int N, int D>
+constexpr int line_radix() {
+  return (D == 2 && N <= 1024) ? 4 : 8;
+}
 
 // --- register-resident launches, dispatched over the power-of-two sizes
-template <typename T, int N, int RR = kR>
+template <typename T, int N, int RR = xpass_radix<T, N>()>
 void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   using SH = XPassShape<N, RR>;
   const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
@@ -98,32 +110,32 @@ void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, int RR = xpass_radix<T, N>()>
 void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
-  using SH = XPassShape<N, kR>;
-  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, kR>::LP * sizeof(cx<T>),
+  using SH = XPassShape<N, RR>;
+  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
                               (size_t)5 * (SH::NTH / 64) * sizeof(double));
   switch (mk) {
     case MAP_LIN:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_LIN_DENS:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_ACC_EM:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_LANCZOS:   // fp64 only
       if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
+        hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
       break;
     default:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, kR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
       break;
   }
 }
 
-template <typename T, int N, int D, int CW, int RR = kR>
+template <typename T, int N, int D, int CW, int RR = line_radix<T, N, D>()>
 void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
   using SH = LineShape<T, N, RR, D, CW>;
   const size_t lds = (size_t)SH::LDS + (size_t)SH::C * a.cpad * sizeof(cx<T>);
@@ -166,10 +178,10 @@ bool pack_pays(int n0, int c, int nsolve, int dev) {
   return (tu + cus - 1) / cus > (tp + cus - 1) / cus;
 }
 
-template <int N>
-int xlines_p2() { return XPassShape<N, kR>::LINES; }
+template <typename T, int N>
+int xlines_p2() { return XPassShape<N, xpass_radix<T, N>()>::LINES; }
 template <typename T, int N, int D>
-int linec_p2() { return LineShape<T, N, kR, D>::C; }
+int linec_p2() { return LineShape<T, N, line_radix<T, N, D>(), D>::C; }
 
 // Tile width of the strided passes: the widest that fits, or a narrower one
 // from SCFFT_LINE_C (a power of two) for tuning.
@@ -205,9 +217,9 @@ int tuned_c(int cmax) {
 // waves resident.
 int r16_linec_f64_2048() { return LineShape<double, 2048, 16, 2>::C; }
 
-int p2_xlines(int n) {
+int p2_xlines(int n, int prec) {
   int r = 1;
-#define C_(N) r = xlines_p2<N>()
+#define C_(N) r = prec == SCFFT_FP32 ? xlines_p2<float, N>() : xlines_p2<double, N>()
   SCFFT_P2_SWITCH(n, C_)
 #undef C_
   return r;
@@ -363,7 +375,7 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && std::getenv("SCFFT_R16");
   p->r16y = false;
   if (p->p2x) {
-    p->xL = p2_xlines(n[0]);
+    p->xL = p2_xlines(n[0], prec);
   } else {
     p->xL = std::max(1, std::min(el / n[0], p->xlines));
   }
@@ -1600,14 +1612,28 @@ scfft_status scfft_estimate_interval_lanczos(const scfft_problem* prob, int step
                                 &n0);
   if (rc != SCFFT_OK) return rc;
   gauss_rule(va, vb, node, w0);
+  // Cullum-Willoughby: a simple node that is also an eigenvalue of T without
+  // its first row and column comes from rounding (lost orthogonality), not
+  // from the measure of v_0; numerically multiple nodes are copies and stay
+  std::vector<double> nhat, whatv;
+  if (va.size() >= 2) {
+    std::vector<double> ah(va.begin() + 1, va.end()), bh(vb.begin() + 1, vb.end());
+    gauss_rule(ah, bh, nhat, whatv);
+  }
   double tot = 0;
   for (double w : w0) tot += w;
   double lo = INFINITY, hi = -INFINITY;
-  for (size_t i = 0; i < node.size(); ++i)
-    if (w0[i] > rel_weight * tot) {
+  for (size_t i = 0; i < node.size(); ++i) {
+    int copies = 0;
+    for (double t : node) copies += std::fabs(t - node[i]) < 1e-8 ? 1 : 0;
+    bool spurious = false;
+    if (copies < 2)
+      for (double t : nhat) spurious = spurious || std::fabs(t - node[i]) < 1e-8;
+    if (!spurious && w0[i] > rel_weight * tot) {
       lo = std::min(lo, node[i]);
       hi = std::max(hi, node[i]);
     }
+  }
   if (!(lo > 0.0) || !(hi < 1.0) || !(lo <= hi)) return SCFFT_ERR_INVALID_ARG;
   const double al = 1.0 / hi - 1.0, be = 1.0 / lo - 1.0;
   // floating-point stability of the accelerated scheme: alpha beta = 1

@@ -401,7 +401,7 @@ def lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="rotated", stream=Non
 
 
 def estimate_interval_lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="rotated",
-                              rel_weight=1e-8, stream=None) -> dict:
+                              rel_weight=1e-6, stream=None) -> dict:
     """scfft_estimate_interval_lanczos: raw and stability-symmetrised interval."""
     prob, keep = make_problem(phase, None, 1.0, e0)
     v = [ctypes.c_double() for _ in range(6)]

@@ -75,7 +75,7 @@ def test_lanczos_full_size_2048_and_accelerated_solve_with_its_interval():
     solve with the interval it recommends converges and matches eq. J47a."""
     chi = torch.as_tensor(inputs.square_array(2048)).cuda()
     iv = scfft.estimate_interval_lanczos(chi, (1.0, 0.0), steps=60)
-    assert abs(iv["mu_min"] - 0.25) < 1e-3 and 0.74 < iv["mu_max"] < 0.7501
+    assert abs(iv["mu_min"] - 0.25) < 1e-3 and 0.74 < iv["mu_max"] < 0.7501, iv
     r = scfft.solve(chi, 100.0, (1, 0), "acc_em", alpha=iv["alpha_used"], beta=iv["beta_used"],
                     tol=1e-10, max_iter=200, fields=False, history=False)
     assert r["status"] == 0

@@ -176,6 +176,86 @@ struct LocalMapR {
     return out;
   }
 
+  // Same step with the phase and the old E_prev value already in registers
+  // (loaded before the inverse FFT, so their latency hides under it).
+  // With SLOTS the H'' slots sv, tv (phase-1 voxels) are prefetched as well.
+  template <bool SLOTS>
+  __device__ __forceinline__ T apply_pf(T raw, bool phk, T epo, T sv, T tv, const Row& w,
+                                        unsigned int k, Acc& acc) const {
+    const T x = invM * raw;
+    T E, J, out;
+    if (MK == MAP_ACC_EM) {
+      if (phk) {
+        if (!SLOTS) {
+          sv = w.S[k];
+          tv = w.Tt[k];
+        }
+        const T s = p1 * x - q2 * sv - q3 * tv;
+        E = inv1w * x + p1kap * s;
+        J = s1 * E;
+        out = z * ((T)2 * p1 * s - x);
+        w.S[k] = -z * ((T)2 * q2 * s - sv);
+        w.Tt[k] = z * ((T)2 * q3 * s - tv);
+      } else {
+        E = inv1w * x;
+        J = E;
+        out = -z * x;
+      }
+    } else if (MK == MAP_ACC_MS) {
+      E = x;
+      if (phk) {
+        if (!SLOTS) sv = w.S[k];
+        const T s = p1 * x - q2 * sv;
+        J = s1 * E;
+        out = z * (x - (T)2 * p1 * s);
+        w.S[k] = z * (sv - (T)2 * q2 * s);
+      } else {
+        J = E;
+        out = z * x;
+      }
+    } else {
+      T ce, co, cj, cs;
+      if (MK == MAP_LIN_DENS) {
+        const T rho = (T)w.rho[k];
+        const T sig = (T)1 + (s1 - (T)1) * rho;
+        if (kind == K_MS) {
+          ce = (T)1;
+          co = (T)1 - sig / s0;
+          cj = sig;
+          cs = (T)0;
+        } else if (kind == K_EM) {
+          ce = (T)1 / (sig + s0);
+          co = (sig - s0) * ce;
+          cj = sig;
+          cs = (T)0;
+        } else {   // adjoint
+          ce = (T)1;
+          co = (sig - s0) / (sig + s0);
+          cj = (T)0;
+          cs = sig / (sig + s0);
+        }
+      } else {
+        const bool ph = phk != 0;
+        ce = ph ? cE[1] : cE[0];
+        co = ph ? cO[1] : cO[0];
+        cj = ph ? cJ[1] : cJ[0];
+        cs = ph ? cS[1] : cS[0];
+      }
+      E = ce * x;
+      J = cj * E;
+      out = co * x + cs * e0c;
+    }
+    acc.Jr += (double)J;
+    acc.e2 += (double)(E * E);
+    acc.eJ += (double)(E * J);
+    if (iter >= 1) {
+      const T dE = E - epo;
+      acc.d2 += (double)(dE * dE);
+    }
+    w.Ep[k] = E;
+    return out;
+  }
+
   __device__ __forceinline__ T apply(T raw, long long g, Acc& acc) const {
     const T x = invM * raw;
     T E, J, out;
@@ -292,19 +372,52 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
     }
     v[i] = mk<T>(av.x - bv.y, av.y + bv.x);   // a + i b
   }
-  cx<T>* slot = lds + line * LP;
-  reg_fft<T, N, R>(v, slot, j, (T)1, tw);
   LocalMapR<T, MK> lm;
   lm.load(a, solve, comp, cbase * a.M);
-  Acc acc;
-  if (valid) {
-    const auto wa = lm.row(rowA * N);
-    const auto wb = lm.row(rowB * N);
+  const auto wa = lm.row(rowA * N);
+  const auto wb = lm.row(rowB * N);
+  // the phase maps and E_prev do not depend on the FFT: load them first
+  constexpr bool PF = MK == MAP_LIN || MK == MAP_ACC_EM || MK == MAP_ACC_MS;
+  // the H'' slots too where registers allow (fp32 with radix 4: measured
+  // faster; at radix 8 or fp64 the extra registers cost a wave per SIMD)
+  constexpr bool PSL = sizeof(T) == 4 && R <= 4;
+  constexpr bool PS = PSL && (MK == MAP_ACC_EM || MK == MAP_ACC_MS);
+  constexpr bool PT = PSL && MK == MAP_ACC_EM;
+  bool pha[R], phb[R];
+  T epa[R], epb[R], sa[R], sb[R], ta[R], tb[R];
+  if (PF && valid) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const unsigned int k = (unsigned int)(j + TL * i);
-      const T oa = lm.apply(v[i].x, wa, k, acc);
-      const T ob = lm.apply(v[i].y, wb, k, acc);
+      pha[i] = wa.ph[k] != 0;
+      phb[i] = wb.ph[k] != 0;
+      epa[i] = wa.Ep[k];
+      epb[i] = wb.Ep[k];
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const unsigned int k = (unsigned int)(j + TL * i);
+      sa[i] = (PS && pha[i]) ? wa.S[k] : (T)0;
+      sb[i] = (PS && phb[i]) ? wb.S[k] : (T)0;
+      ta[i] = (PT && pha[i]) ? wa.Tt[k] : (T)0;
+      tb[i] = (PT && phb[i]) ? wb.Tt[k] : (T)0;
+    }
+  }
+  cx<T>* slot = lds + line * LP;
+  reg_fft<T, N, R>(v, slot, j, (T)1, tw);
+  Acc acc;
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const unsigned int k = (unsigned int)(j + TL * i);
+      T oa, ob;
+      if (PF) {
+        oa = lm.template apply_pf<PSL>(v[i].x, pha[i], epa[i], sa[i], ta[i], wa, k, acc);
+        ob = lm.template apply_pf<PSL>(v[i].y, phb[i], epb[i], sb[i], tb[i], wb, k, acc);
+      } else {
+        oa = lm.apply(v[i].x, wa, k, acc);
+        ob = lm.apply(v[i].y, wb, k, acc);
+      }
       v[i] = mk<T>(oa, ob);
     }
   }

@@ -178,6 +178,19 @@ struct LocalMap {
   }
 
   __device__ __forceinline__ cx<T> apply(cx<T> raw, long long g, Acc& acc) const {
+    return apply_core<false>(raw, g, false, mk<T>(0, 0), acc);
+  }
+
+  // Same step with the phase and the old E_prev value already in registers
+  // (loaded before the inverse FFT, so their latency hides under it).
+  __device__ __forceinline__ cx<T> apply_pf(cx<T> raw, long long g, bool phv, cx<T> epo,
+                                            Acc& acc) const {
+    return apply_core<true>(raw, g, phv, epo, acc);
+  }
+
+  template <bool PF>
+  __device__ __forceinline__ cx<T> apply_core(cx<T> raw, long long g, bool phv, cx<T> epo,
+                                              Acc& acc) const {
     const cx<T> x = invM * raw;
     cx<T> E, J, out;
     const bool lz = MK == MAP_ANY ? kind == K_LANCZOS : MK == MAP_LANCZOS;
@@ -208,7 +221,7 @@ struct LocalMap {
     const bool dens_kind = MK == MAP_ANY ? density != 0 : MK == MAP_LIN_DENS;
     if (acc_kind) {
       const T two = (T)2;
-      const int ph = phase[g];
+      const int ph = PF ? (int)phv : phase[g];
       if (acc_em) {
         if (ph) {
           // phase 1 of H'': s = p^T (Q, S, T); Z'' = z (2 p p^T - I)
@@ -263,7 +276,7 @@ struct LocalMap {
           }
         }
       } else {
-        const bool ph = phase[g] != 0;
+        const bool ph = PF ? phv : phase[g] != 0;
         ce = ph ? cE[1] : cE[0];
         co = ph ? cO[1] : cO[0];
         cj = ph ? cJ[1] : cJ[0];
@@ -277,7 +290,7 @@ struct LocalMap {
     acc.Ji += (double)J.y;
     acc.e2 += (double)norm2(E);
     acc.eJ += (double)(E.x * J.x + E.y * J.y);
-    if (iter >= 1) acc.d2 += (double)norm2(E - Ep[g]);
+    if (iter >= 1) acc.d2 += (double)norm2(E - (PF ? epo : Ep[g]));
     Ep[g] = E;
     return out;
   }

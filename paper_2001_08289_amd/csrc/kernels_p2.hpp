@@ -65,14 +65,29 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_p2_kernel(XArgs
   cx<T> v[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) v[i] = valid ? X[j + TL * i] : mk<T>(0, 0);
-  cx<T>* slot = lds + line * LP;
-  reg_fft<T, N, R>(v, slot, j, (T)1, tw);
   LocalMap<T, MK> lm;
   lm.load(a, solve, comp, fbase);
+  // the phase map and E_prev do not depend on the FFT: load them first
+  constexpr bool PF = MK == MAP_LIN || MK == MAP_ACC_EM || MK == MAP_ACC_MS;
+  bool ph[R];
+  cx<T> epo[R];
+  if (PF && valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const long long g = base + j + TL * i;
+      ph[i] = lm.phase[g] != 0;
+      epo[i] = lm.Ep[g];
+    }
+  }
+  cx<T>* slot = lds + line * LP;
+  reg_fft<T, N, R>(v, slot, j, (T)1, tw);
   Acc acc;
   if (valid) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) v[i] = lm.apply(v[i], base + j + TL * i, acc);
+    for (int i = 0; i < R; ++i) {
+      const long long g = base + j + TL * i;
+      v[i] = PF ? lm.apply_pf(v[i], g, ph[i], epo[i], acc) : lm.apply(v[i], g, acc);
+    }
   }
   reg_fft<T, N, R>(v, slot, j, (T)-1, tw);
   if (valid) {

@@ -125,16 +125,26 @@ struct LineShape {
   static constexpr int LDS = C * LP * (int)sizeof(cx<T>) * D;
 };
 
-// Symbol vector of eq. J11 on the grid for one mode, compile-time dimension.
+// The two per-axis symbol-table entries of mode m (see symbol_table_kernel).
 template <typename T, int D>
-__device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* nv) {
-  if (a.symbol == SYM_ROTATED) {
+__device__ __forceinline__ void symbol_entries(const GArgs& a, const int* m, T (*tv)[2]) {
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const double* t = a.symtab[q] + 2 * m[q];
+    tv[q][0] = (T)t[0];
+    tv[q][1] = (T)t[1];
+  }
+}
+
+// Symbol vector of eq. J11 on the grid for one mode from its table entries.
+template <typename T, int D>
+__device__ __forceinline__ T mode_symbol_t(int symbol, const T (*tv)[2], cx<T>* nv) {
+  if (symbol == SYM_ROTATED) {
     T s[D], c[D];
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      const double* t = a.symtab[q] + 2 * m[q];
-      s[q] = (T)t[0];
-      c[q] = (T)t[1];
+      s[q] = tv[q][0];
+      c[q] = tv[q][1];
     }
     T nrm = 0;
 #pragma unroll
@@ -156,15 +166,14 @@ __device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* 
       }
     }
     return nrm;
-  } else if (a.symbol == SYM_SPECTRAL) {
+  } else if (symbol == SYM_SPECTRAL) {
     T v[D];
     bool nyq[D];
     bool has_nyq = false, has_other = false;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      const double* t = a.symtab[q] + 2 * m[q];
-      v[q] = (T)t[0];
-      nyq[q] = t[1] != 0.0;
+      v[q] = tv[q][0];
+      nyq[q] = tv[q][1] != (T)0;
       has_nyq |= nyq[q];
       has_other |= (!nyq[q]) && (v[q] != (T)0);
     }
@@ -180,8 +189,7 @@ __device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* 
     T nrm = 0;
 #pragma unroll
     for (int q = 0; q < D; ++q) {
-      const double* t = a.symtab[q] + 2 * m[q];
-      nv[q] = mk<T>((T)t[0], (T)t[1]);
+      nv[q] = mk<T>(tv[q][0], tv[q][1]);
       nrm += norm2(nv[q]);
     }
     return nrm;
@@ -193,7 +201,7 @@ __device__ __forceinline__ T mode_symbol_d(const GArgs& a, const int* m, cx<T>* 
 // w <- ga w + gb n (n . w) / |n|^2 with the symbol vector n of the mode.
 template <typename T, int D>
 __device__ __forceinline__ void gamma_mode(const GArgs& a, const SolveCoef& cf, T ga, T gb, T keep,
-                                           const int* m, cx<T>* w) {
+                                           const int* m, const T (*tv)[2], cx<T>* w) {
   const bool zero = (m[0] == 0) && (m[1] == 0) && (D == 2 || m[2] == 0);
   if (zero) {
 #pragma unroll
@@ -201,7 +209,7 @@ __device__ __forceinline__ void gamma_mode(const GArgs& a, const SolveCoef& cf, 
     return;
   }
   cx<T> nv[3];
-  const T nrm = mode_symbol_d<T, D>(a, m, nv);
+  const T nrm = mode_symbol_t<T, D>(a.symbol, tv, nv);
   cx<T> dot = mk<T>(0, 0);
   if (a.symbol == SYM_NETWORK) {
 #pragma unroll
@@ -271,6 +279,23 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
     for (int i = 0; i < R; ++i)
       v[cc][i] = valid ? X[cc * Mu + lane_off + (unsigned int)(TL * i) * su] : mk<T>(0, 0);
   cx<T>* slot = lds + c * (D * LP + a.cpad);
+  // symbol-table entries of this thread's modes: loaded before the FFT so
+  // their latency hides under it
+  T tab[R][D][2];
+  if (gam && valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      int m[3];
+      m[0] = x0 + c;
+      if (D == 2) {
+        m[1] = j + TL * i;
+      } else {
+        m[1] = by;
+        m[2] = j + TL * i;
+      }
+      symbol_entries<T, D>(a, m, tab[i]);
+    }
+  }
   if (a.mode != 2) reg_fft_multi<T, N, R, SH::PAD, D>(v, slot, LP, j, (T)-1, tw);
   // 2D real mode: column 0 of tile 0 carries kx = 0 in its real and
   // kx = n0/2 in its imaginary part, both real along y, so after the y-FFT
@@ -315,12 +340,14 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
           b[cc] = mk<T>((T)0.5 * df.y, (T)-0.5 * df.x);
         }
         const int mn[3] = {a.n[0], m[1], 0};   // kx = n0/2 (= the column count)
-        gamma_mode<T, D>(a, cf, ga, gb, keep, m, w);
-        gamma_mode<T, D>(a, cf, ga, gb, keep, mn, b);
+        T tn[D][2];
+        symbol_entries<T, D>(a, mn, tn);
+        gamma_mode<T, D>(a, cf, ga, gb, keep, m, tab[i], w);
+        gamma_mode<T, D>(a, cf, ga, gb, keep, mn, tn, b);
 #pragma unroll
         for (int cc = 0; cc < D; ++cc) v[cc][i] = mk<T>(w[cc].x - b[cc].y, w[cc].y + b[cc].x);
       } else {
-        gamma_mode<T, D>(a, cf, ga, gb, keep, m, w);
+        gamma_mode<T, D>(a, cf, ga, gb, keep, m, tab[i], w);
 #pragma unroll
         for (int cc = 0; cc < D; ++cc) v[cc][i] = w[cc];
       }

@@ -228,12 +228,15 @@ __device__ __forceinline__ void stockham_pass(cx<T>* lds, int nl, int n, int ns,
       }
       const int k = j % ns;
       if (ns > 1) {
+        // one table load per butterfly; the powers w^q follow by products
+        cx<T> w1 = tw[k * step];
+        if (sign > 0) w1.y = -w1.y;
+        cx<T> wq[R];
+        wq[1] = w1;
 #pragma unroll
-        for (int q = 1; q < R; ++q) {
-          cx<T> w = tw[k * q * step];
-          if (sign > 0) w.y = -w.y;
-          v[u][q] = v[u][q] * w;
-        }
+        for (int q = 2; q < R; ++q) wq[q] = (q & 1) ? wq[q - 1] * w1 : wq[q / 2] * wq[q / 2];
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[u][q] = v[u][q] * wq[q];
       }
       Dft<T, R>::run(v[u], sign);
       const int idxd = (j / ns) * ns * R + k;

@@ -25,7 +25,7 @@ using cd = std::complex<double>;
 namespace scfft {
 namespace {
 
-constexpr int kNT = 256;
+constexpr int kNT = 1024;
 // elements a workgroup transforms at once (64 KiB of LDS in both precisions)
 constexpr int kElemsF32 = 8192;
 constexpr int kElemsF64 = 4096;

@@ -106,8 +106,6 @@ struct GArgs {
   int ignore_done;
   int mode;             // 0: Gamma pass; 1: forward FFT only; 2: inverse FFT only
   int fin;              // 1: workgroup (0,0) of each solve also runs finalize_solve
-  int lmap;             // register passes: 0 column index fastest in the workgroup, 1 line index fastest
-  int cpad;             // register passes: extra LDS elements between the slots of adjacent columns
   int packed;           // 2D real mode: column 0 holds kx = 0 (real part) and kx = n0/2 (imaginary)
   FArgs f;
 };

@@ -254,8 +254,8 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
     if (blockIdx.y == 0 && comp0 == 0) finalize_solve(a.f, solve, tid, SH::NTH);
     return;
   }
-  const int c = a.lmap ? tid / TL : tid % C;
-  const int j = a.lmap ? tid - c * TL : tid / C;
+  const int c = tid % C;
+  const int j = tid / C;
   // XCD-aware tile order
   const int nb = nbx * nby;
   const int b = blockIdx.y * nbx + blockIdx.x;
@@ -278,7 +278,7 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
 #pragma unroll
     for (int i = 0; i < R; ++i)
       v[cc][i] = valid ? X[cc * Mu + lane_off + (unsigned int)(TL * i) * su] : mk<T>(0, 0);
-  cx<T>* slot = lds + c * (D * LP + a.cpad);
+  cx<T>* slot = lds + c * D * LP;
   // symbol-table entries of this thread's modes: loaded before the FFT so
   // their latency hides under it
   T tab[R][D][2];

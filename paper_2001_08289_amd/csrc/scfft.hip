@@ -138,7 +138,7 @@ void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
 template <typename T, int N, int D, int CW, int RR = line_radix<T, N, D>()>
 void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
   using SH = LineShape<T, N, RR, D, CW>;
-  const size_t lds = (size_t)SH::LDS + (size_t)SH::C * a.cpad * sizeof(cx<T>);
+  const size_t lds = (size_t)SH::LDS;
   if (lds > 65536) {
     // LDS beyond 64 KiB per workgroup (gfx950 has 160 KiB per CU) is opt-in
     static size_t set = 0;
@@ -185,11 +185,6 @@ int linec_p2() { return LineShape<T, N, line_radix<T, N, D>(), D>::C; }
 
 // Tile width of the strided passes: the widest that fits, or a narrower one
 // from SCFFT_LINE_C (a power of two) for tuning.
-int env_int(const char* name, int dflt) {
-  const char* e = std::getenv(name);
-  return e ? std::atoi(e) : dflt;
-}
-
 int tuned_c(int cmax) {
   const char* e = std::getenv("SCFFT_LINE_C");
   if (!e) return cmax;
@@ -387,7 +382,7 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
                            : std::min(pow2_floor(std::max(1, el / n[1])), n[0]))
                  : 1;
   // the packed column is unpacked by the register Gamma pass (2D)
-  p->packed = real && d == 2 && p->p2g && !std::getenv("SCFFT_NO_PACK") &&
+  p->packed = real && d == 2 && p->p2g &&
               (p->r16g || pack_pays(n[0], p->gC, nsolve, dev));
   if (p->packed) p->H = n[0] / 2;
   p->Mh = (long long)p->H * n[1] * n2;
@@ -687,8 +682,6 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
   g.f = f;
   g.fin = 0;
   g.packed = p->packed ? 1 : 0;
-  g.lmap = env_int("SCFFT_LMAP", 0);
-  g.cpad = env_int("SCFFT_CPAD", 0);
   for (int a = 0; a < d; ++a) g.symtab[a] = p->sym[a];
   if (d == 3) {
     GArgs y = g;

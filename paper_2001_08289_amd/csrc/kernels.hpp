@@ -348,7 +348,7 @@ __global__ __launch_bounds__(NT) void xpass_kernel(XArgs a) {
   if (tid < 5) {
     double s = 0;
     for (int w = 0; w < NT / 64; ++w) s += red[tid * (NT / 64) + w];
-    a.part[(((long long)solve * a.d + comp) * gridDim.x + blockIdx.x) * 5 + tid] = s;
+    a.part[(((long long)solve * a.d + comp) * 5 + tid) * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -611,14 +611,28 @@ __device__ __forceinline__ void finalize_solve(const FArgs& a, int solve, int ti
   const int nt = (nth >= 64 && nth % 64 == 0) ? nth : 1;
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (tid < nt) {
+    // partials are [solve][component][quantity][block]: every quantity is one
+    // contiguous run, read coalesced, with 4 blocks x 5 quantities in flight
     for (int c = 0; c < d; ++c) {
-      const double* p = a.part + ((long long)solve * d + c) * a.nblocks * 5;
-      for (int b = tid; b < a.nblocks; b += nt) {
-        acc[2 * c] += p[b * 5 + 0];
-        acc[2 * c + 1] += p[b * 5 + 1];
-        acc[6] += p[b * 5 + 2];
-        acc[7] += p[b * 5 + 3];
-        acc[8] += p[b * 5 + 4];
+      const double* p = a.part + ((long long)solve * d + c) * 5 * a.nblocks;
+      constexpr int U = 4;
+      for (int b0 = tid; b0 < a.nblocks; b0 += U * nt) {
+        double v[U][5];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            const int b = b0 + u * nt;
+            v[u][q] = b < a.nblocks ? p[(long long)q * a.nblocks + b] : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          acc[2 * c] += v[u][0];
+          acc[2 * c + 1] += v[u][1];
+          acc[6] += v[u][2];
+          acc[7] += v[u][3];
+          acc[8] += v[u][4];
+        }
       }
     }
   }

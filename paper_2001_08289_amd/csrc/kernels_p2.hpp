@@ -9,9 +9,11 @@
 
 namespace scfft {
 
-// Block reduction of the five fp64 partial sums (wave64 shuffles, then LDS).
+// Block reduction of the five fp64 partial sums (wave64 shuffles, then LDS);
+// quantity k goes to out[k * stride].
 template <int NTH>
-__device__ __forceinline__ void block_reduce5(Acc acc, double* red_lds, double* out, int tid) {
+__device__ __forceinline__ void block_reduce5(Acc acc, double* red_lds, double* out, long long stride,
+                                              int tid) {
   double v[5] = {acc.Jr, acc.Ji, acc.e2, acc.d2, acc.eJ};
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
@@ -30,7 +32,7 @@ __device__ __forceinline__ void block_reduce5(Acc acc, double* red_lds, double* 
   if (tid < 5) {
     double s = 0;
     for (int w = 0; w < NW; ++w) s += red_lds[tid * NW + w];
-    out[tid] = s;
+    out[tid * stride] = s;
   }
 }
 
@@ -96,7 +98,8 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_p2_kernel(XArgs
   }
   __syncthreads();   // the FFT slots are free again
   block_reduce5<NTH>(acc, reinterpret_cast<double*>(smem_raw),
-                     a.part + (((long long)solve * a.d + comp) * gridDim.x + blockIdx.x) * 5, tid);
+                     a.part + ((long long)solve * a.d + comp) * 5 * gridDim.x + blockIdx.x,
+                     gridDim.x, tid);
 }
 
 // Lines per workgroup of the strided passes.  Every line keeps D LDS slots
@@ -248,17 +251,19 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
   // The first pass after the x pass also reduces its partials and applies
   // the stop rules: the grid then has one extra column of workgroups, and the
   // one at y = 0 of each solve does only that, beside the FFT tiles rather
-  // than in front of one of them.
+  // than in front of one of them (in a grid of one row it is dispatched
+  // last, so it does not hold a CU slot that a tile needs).
   const int nbx = gridDim.x - (a.fin ? 1 : 0), nby = gridDim.y;
   if (a.fin && (int)blockIdx.x == nbx) {
     if (blockIdx.y == 0 && comp0 == 0) finalize_solve(a.f, solve, tid, SH::NTH);
     return;
   }
+  const int bxi = (int)blockIdx.x;
   const int c = tid % C;
   const int j = tid / C;
   // XCD-aware tile order
   const int nb = nbx * nby;
-  const int b = blockIdx.y * nbx + blockIdx.x;
+  const int b = blockIdx.y * nbx + bxi;
   int t = b;
   const int full = nb - nb % 8;
   if (b < full) t = (b % 8) * (full / 8) + b / 8;

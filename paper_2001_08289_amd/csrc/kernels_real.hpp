@@ -455,7 +455,7 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   }
   __syncthreads();
   block_reduce5<NTH>(acc, reinterpret_cast<double*>(smem_raw),
-                     a.part + (cbase * gridDim.x + blockIdx.x) * 5, tid);
+                     a.part + cbase * 5 * gridDim.x + blockIdx.x, gridDim.x, tid);
 }
 
 struct InitRArgs {

@@ -11,10 +11,11 @@
 //   part  [b][c][xblocks][5] double: per-workgroup partial sums.
 //
 // One iteration (2D): x pass (inverse x-FFT, physical field, reductions,
-// local map, forward x-FFT) -> finalize (fp64 reductions, stop rules) ->
-// Gamma pass (forward y-FFT, Gamma_1 of eq. J11 / J44-J45 fused with the
-// scheme's k = 0 source term, inverse y-FFT).  3D adds a forward y pass
-// before and an inverse y pass after the Gamma pass (which then runs along z).
+// local map, forward x-FFT) -> Gamma pass (forward y-FFT, Gamma_1 of eq. J11 /
+// J44-J45 fused with the scheme's k = 0 source term, inverse y-FFT; one extra
+// workgroup per solve reduces the x pass's fp64 partials and applies the stop
+// rules).  3D adds a forward y pass before and an inverse y pass after the
+// Gamma pass (which then runs along z).
 #pragma once
 
 #include "device_fft.hpp"
@@ -105,7 +106,7 @@ struct GArgs {
   int d, C, stride, symbol;
   int ignore_done;
   int mode;             // 0: Gamma pass; 1: forward FFT only; 2: inverse FFT only
-  int fin;              // 1: workgroup (0,0) of each solve also runs finalize_solve
+  int fin;              // 1: one extra workgroup per solve runs finalize_solve
   int packed;           // 2D real mode: column 0 holds kx = 0 (real part) and kx = n0/2 (imaginary)
   FArgs f;
 };

@@ -248,8 +248,8 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
-  // The first pass after the x pass also reduces its partials and applies
-  // the stop rules: the grid then has one extra column of workgroups, and the
+  // The Gamma pass also reduces the x pass's partials and applies the stop
+  // rules: the grid then has one extra column of workgroups, and the
   // one at y = 0 of each solve does only that, beside the FFT tiles rather
   // than in front of one of them (in a grid of one row it is dispatched
   // last, so it does not hold a CU slot that a tile needs).

@@ -690,11 +690,10 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     y.C = p->yC;
     y.stride = p->H;
     y.mode = 1;
-    y.fin = 1;   // first pass after the x pass
+    y.fin = 0;   // the stop rules run in the Gamma pass (measured cheaper there)
     dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(4);
     if (p->p2y) {
-      grid.x += 1;   // the finalizing workgroups
 #define C_(N) launch_line_p2<T, N, 1>(y, grid, st)
       SCFFT_P2_SWITCH(p->n[1], C_)
 #undef C_
@@ -712,7 +711,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     q.C = p->gC;
     q.stride = d == 2 ? p->H : p->H * p->n[1];
     q.mode = 0;
-    q.fin = d == 2 ? 1 : 0;
+    q.fin = 1;
     dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
     if ((p->r16g || p->p2g) && q.fin) grid.x += 1;   // the finalizing workgroups
     rec(6);

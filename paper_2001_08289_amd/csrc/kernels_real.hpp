@@ -104,76 +104,9 @@ struct LocalMapR {
   }
 
   __device__ __forceinline__ T apply(T raw, const Row& w, unsigned int k, Acc& acc) const {
-    const T x = invM * raw;
-    T E, J, out;
-    if (MK == MAP_LANCZOS) return lanczos(x, w.ph[k] != 0, w.S[k], w.Ep[k], acc);
-    if (MK == MAP_ACC_EM) {
-      if (w.ph[k]) {
-        const T sv = w.S[k], tv = w.Tt[k];
-        const T s = p1 * x - q2 * sv - q3 * tv;
-        E = inv1w * x + p1kap * s;
-        J = s1 * E;
-        out = z * ((T)2 * p1 * s - x);
-        w.S[k] = -z * ((T)2 * q2 * s - sv);
-        w.Tt[k] = z * ((T)2 * q3 * s - tv);
-      } else {
-        E = inv1w * x;
-        J = E;
-        out = -z * x;
-      }
-    } else if (MK == MAP_ACC_MS) {
-      E = x;
-      if (w.ph[k]) {
-        const T sv = w.S[k];
-        const T s = p1 * x - q2 * sv;
-        J = s1 * E;
-        out = z * (x - (T)2 * p1 * s);
-        w.S[k] = z * (sv - (T)2 * q2 * s);
-      } else {
-        J = E;
-        out = z * x;
-      }
-    } else {
-      T ce, co, cj, cs;
-      if (MK == MAP_LIN_DENS) {
-        const T rho = (T)w.rho[k];
-        const T sig = (T)1 + (s1 - (T)1) * rho;
-        if (kind == K_MS) {
-          ce = (T)1;
-          co = (T)1 - sig / s0;
-          cj = sig;
-          cs = (T)0;
-        } else if (kind == K_EM) {
-          ce = (T)1 / (sig + s0);
-          co = (sig - s0) * ce;
-          cj = sig;
-          cs = (T)0;
-        } else {   // adjoint
-          ce = (T)1;
-          co = (sig - s0) / (sig + s0);
-          cj = (T)0;
-          cs = sig / (sig + s0);
-        }
-      } else {
-        const bool ph = w.ph[k] != 0;
-        ce = ph ? cE[1] : cE[0];
-        co = ph ? cO[1] : cO[0];
-        cj = ph ? cJ[1] : cJ[0];
-        cs = ph ? cS[1] : cS[0];
-      }
-      E = ce * x;
-      J = cj * E;
-      out = co * x + cs * e0c;
-    }
-    acc.Jr += (double)J;
-    acc.e2 += (double)(E * E);
-    acc.eJ += (double)(E * J);
-    if (iter >= 1) {
-      const T dE = E - w.Ep[k];
-      acc.d2 += (double)(dE * dE);
-    }
-    w.Ep[k] = E;
-    return out;
+    if (MK == MAP_LANCZOS) return lanczos(invM * raw, w.ph[k] != 0, w.S[k], w.Ep[k], acc);
+    const bool ph = MK == MAP_LIN_DENS ? false : w.ph[k] != 0;
+    return apply_pf<false>(raw, ph, w.Ep[k], (T)0, (T)0, w, k, acc);
   }
 
   // Same step with the phase and the old E_prev value already in registers
@@ -256,78 +189,6 @@ struct LocalMapR {
     return out;
   }
 
-  __device__ __forceinline__ T apply(T raw, long long g, Acc& acc) const {
-    const T x = invM * raw;
-    T E, J, out;
-    if (MK == MAP_LANCZOS) return lanczos(x, phase[g] != 0, S[g], Ep[g], acc);
-    if (MK == MAP_ACC_EM) {
-      if (phase[g]) {
-        const T sv = S[g], tv = Tt[g];
-        const T s = p1 * x - q2 * sv - q3 * tv;
-        E = inv1w * x + p1kap * s;
-        J = s1 * E;
-        out = z * ((T)2 * p1 * s - x);
-        S[g] = -z * ((T)2 * q2 * s - sv);
-        Tt[g] = z * ((T)2 * q3 * s - tv);
-      } else {
-        E = inv1w * x;
-        J = E;
-        out = -z * x;
-      }
-    } else if (MK == MAP_ACC_MS) {
-      E = x;
-      if (phase[g]) {
-        const T sv = S[g];
-        const T s = p1 * x - q2 * sv;
-        J = s1 * E;
-        out = z * (x - (T)2 * p1 * s);
-        S[g] = z * (sv - (T)2 * q2 * s);
-      } else {
-        J = E;
-        out = z * x;
-      }
-    } else {
-      T ce, co, cj, cs;
-      if (MK == MAP_LIN_DENS) {
-        const T rho = (T)dens[g];
-        const T sig = (T)1 + (s1 - (T)1) * rho;
-        if (kind == K_MS) {
-          ce = (T)1;
-          co = (T)1 - sig / s0;
-          cj = sig;
-          cs = (T)0;
-        } else if (kind == K_EM) {
-          ce = (T)1 / (sig + s0);
-          co = (sig - s0) * ce;
-          cj = sig;
-          cs = (T)0;
-        } else {   // adjoint
-          ce = (T)1;
-          co = (sig - s0) / (sig + s0);
-          cj = (T)0;
-          cs = sig / (sig + s0);
-        }
-      } else {
-        const bool ph = phase[g] != 0;
-        ce = ph ? cE[1] : cE[0];
-        co = ph ? cO[1] : cO[0];
-        cj = ph ? cJ[1] : cJ[0];
-        cs = ph ? cS[1] : cS[0];
-      }
-      E = ce * x;
-      J = cj * E;
-      out = co * x + cs * e0c;
-    }
-    acc.Jr += (double)J;
-    acc.e2 += (double)(E * E);
-    acc.eJ += (double)(E * J);
-    if (iter >= 1) {
-      const T dE = E - Ep[g];
-      acc.d2 += (double)(dE * dE);
-    }
-    Ep[g] = E;
-    return out;
-  }
 };
 
 // x pass, real mode: LINES complex lines = 2*LINES real rows of one component.

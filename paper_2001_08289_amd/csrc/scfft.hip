@@ -208,7 +208,8 @@ int tuned_c(int cmax) {
   }
 
 // Radix 16 (2048 = 16*8*16, one LDS exchange fewer) measured faster only for
-// the fp64 Gamma pass of 2048^2 grids; everywhere else radix 8 keeps more
+// the fp64 Gamma pass of 2048^2 grids (115 -> 104 us), where it is the
+// default (SCFFT_R16=0 turns it off); everywhere else radix 8 or 4 keeps more
 // waves resident.
 int r16_linec_f64_2048() { return LineShape<double, 2048, 16, 2>::C; }
 
@@ -367,7 +368,10 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   p->H = real ? n[0] / 2 + 1 : n[0];
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
   p->r16x = false;
-  p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && std::getenv("SCFFT_R16");
+  {
+    const char* e = std::getenv("SCFFT_R16");
+    p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && !(e && std::atoi(e) == 0);
+  }
   p->r16y = false;
   if (p->p2x) {
     p->xL = p2_xlines(n[0], prec);

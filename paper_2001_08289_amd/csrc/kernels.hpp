@@ -121,6 +121,18 @@ struct Acc {
   double Jr = 0, Ji = 0, e2 = 0, d2 = 0, eJ = 0;
 };
 
+// Makes the fp64 accumulation happen voxel by voxel in an unrolled loop.
+// Without it the compiler sinks every voxel's conversions and adds below the
+// map's last per-voxel branch (the H'' slots of phase-1 voxels), so all the
+// voxels' E and J values stay live at once: the 2048-point fp32 x pass then
+// needs 134 VGPRs (three waves per SIMD) instead of 120 (four).  The empty asm
+// emits nothing; it only marks the accumulators as used and redefined here.
+template <bool CPLX>
+__device__ __forceinline__ void acc_settle(Acc& acc) {
+  if (CPLX) asm volatile("" : "+v"(acc.Jr), "+v"(acc.Ji), "+v"(acc.e2), "+v"(acc.d2), "+v"(acc.eJ));
+  else asm volatile("" : "+v"(acc.Jr), "+v"(acc.e2), "+v"(acc.d2), "+v"(acc.eJ));
+}
+
 // The scheme's pointwise step at one voxel: from the scaled iterate x it
 // forms the physical field E (the Q-slot of E'' in H''), the current J, the
 // fp64 reduction terms (sum J, |E|^2, |E - E_prev|^2, Re conj(E) J), stores E

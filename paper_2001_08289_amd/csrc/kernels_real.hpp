@@ -244,6 +244,10 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   constexpr bool PSL = sizeof(T) == 4 && R <= 4;
   constexpr bool PS = PSL && (MK == MAP_ACC_EM || MK == MAP_ACC_MS);
   constexpr bool PT = PSL && MK == MAP_ACC_EM;
+  // voxel-by-voxel fp64 accumulation where the map branches per voxel and
+  // the slots are not already in registers (fewer VGPRs there; elsewhere
+  // it measured neutral or a few registers worse)
+  constexpr bool SETTLE = (MK == MAP_LIN_DENS || MK == MAP_ACC_EM || MK == MAP_ACC_MS) && !PSL;
   bool pha[R], phb[R];
   T epa[R], epb[R], sa[R], sb[R], ta[R], tb[R];
   if (PF && valid) {
@@ -280,6 +284,7 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
         ob = lm.apply(v[i].y, wb, k, acc);
       }
       v[i] = mk<T>(oa, ob);
+      if (SETTLE) acc_settle<false>(acc);
     }
   }
   reg_fft<T, N, R>(v, slot, j, (T)-1, tw);

@@ -22,7 +22,24 @@
 
 namespace scfft {
 
-template <typename T, int MK>
+// Loads and stores of the streams only the x pass uses (phase map, E_prev,
+// H'' slots).  NT marks them nontemporal: where an iteration's arrays do not
+// fit in the 256 MB Infinity Cache, that keeps the half spectrum the x pass
+// writes there for the next pass (256^3 fp32: forward y pass 107 -> 62 us);
+// where they fit it costs (2048^2 fp32 x pass 41 -> 47 us), so it is chosen
+// per plan.
+template <bool NT, typename U>
+__device__ __forceinline__ U ld_x(const U* p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT, typename U>
+__device__ __forceinline__ void st_x(U* p, U v) {
+  if (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename T, int MK, bool NT = false>
 struct LocalMapR {
   int iter, kind;
   T cE[2], cO[2], cJ[2], cS[2];
@@ -120,15 +137,15 @@ struct LocalMapR {
     if (MK == MAP_ACC_EM) {
       if (phk) {
         if (!SLOTS) {
-          sv = w.S[k];
-          tv = w.Tt[k];
+          sv = ld_x<NT>(&w.S[k]);
+          tv = ld_x<NT>(&w.Tt[k]);
         }
         const T s = p1 * x - q2 * sv - q3 * tv;
         E = inv1w * x + p1kap * s;
         J = s1 * E;
         out = z * ((T)2 * p1 * s - x);
-        w.S[k] = -z * ((T)2 * q2 * s - sv);
-        w.Tt[k] = z * ((T)2 * q3 * s - tv);
+        st_x<NT>(&w.S[k], -z * ((T)2 * q2 * s - sv));
+        st_x<NT>(&w.Tt[k], z * ((T)2 * q3 * s - tv));
       } else {
         E = inv1w * x;
         J = E;
@@ -137,11 +154,11 @@ struct LocalMapR {
     } else if (MK == MAP_ACC_MS) {
       E = x;
       if (phk) {
-        if (!SLOTS) sv = w.S[k];
+        if (!SLOTS) sv = ld_x<NT>(&w.S[k]);
         const T s = p1 * x - q2 * sv;
         J = s1 * E;
         out = z * (x - (T)2 * p1 * s);
-        w.S[k] = z * (sv - (T)2 * q2 * s);
+        st_x<NT>(&w.S[k], z * (sv - (T)2 * q2 * s));
       } else {
         J = E;
         out = z * x;
@@ -185,14 +202,14 @@ struct LocalMapR {
       const T dE = E - epo;
       acc.d2 += (double)(dE * dE);
     }
-    w.Ep[k] = E;
+    st_x<NT>(&w.Ep[k], E);
     return out;
   }
 
 };
 
 // x pass, real mode: LINES complex lines = 2*LINES real rows of one component.
-template <typename T, int N, int R, int MK>
+template <typename T, int N, int R, int MK, bool NT>
 __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArgs a) {
   using SH = XPassShape<N, R>;
   constexpr int TL = SH::TL, LINES = SH::LINES, NTH = SH::NTH;
@@ -233,7 +250,7 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
     }
     v[i] = mk<T>(av.x - bv.y, av.y + bv.x);   // a + i b
   }
-  LocalMapR<T, MK> lm;
+  LocalMapR<T, MK, NT> lm;
   lm.load(a, solve, comp, cbase * a.M);
   const auto wa = lm.row(rowA * N);
   const auto wb = lm.row(rowB * N);
@@ -254,18 +271,18 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const unsigned int k = (unsigned int)(j + TL * i);
-      pha[i] = wa.ph[k] != 0;
-      phb[i] = wb.ph[k] != 0;
-      epa[i] = wa.Ep[k];
-      epb[i] = wb.Ep[k];
+      pha[i] = ld_x<NT>(&wa.ph[k]) != 0;
+      phb[i] = ld_x<NT>(&wb.ph[k]) != 0;
+      epa[i] = ld_x<NT>(&wa.Ep[k]);
+      epb[i] = ld_x<NT>(&wb.Ep[k]);
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const unsigned int k = (unsigned int)(j + TL * i);
-      sa[i] = (PS && pha[i]) ? wa.S[k] : (T)0;
-      sb[i] = (PS && phb[i]) ? wb.S[k] : (T)0;
-      ta[i] = (PT && pha[i]) ? wa.Tt[k] : (T)0;
-      tb[i] = (PT && phb[i]) ? wb.Tt[k] : (T)0;
+      sa[i] = (PS && pha[i]) ? ld_x<NT>(&wa.S[k]) : (T)0;
+      sb[i] = (PS && phb[i]) ? ld_x<NT>(&wb.S[k]) : (T)0;
+      ta[i] = (PT && pha[i]) ? ld_x<NT>(&wa.Tt[k]) : (T)0;
+      tb[i] = (PT && phb[i]) ? ld_x<NT>(&wb.Tt[k]) : (T)0;
     }
   }
   cx<T>* slot = lds + line * LP;

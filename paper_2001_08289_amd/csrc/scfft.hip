@@ -68,6 +68,9 @@ int pow2_floor(int v) {
 }
 
 
+// MI355X Infinity Cache (last-level cache in front of HBM)
+constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
+
 bool is_p2(int n) { return n >= 16 && n <= 4096 && (n & (n - 1)) == 0; }
 
 
@@ -85,29 +88,35 @@ constexpr int line_radix() {
 }
 
 // --- register-resident launches, dispatched over the power-of-two sizes
-template <typename T, int N, int RR = xpass_radix<T, N>()>
-void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
+template <typename T, int N, bool NT, int RR = xpass_radix<T, N>()>
+void launch_xpass_r2c_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   using SH = XPassShape<N, RR>;
   const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
                               (size_t)5 * (SH::NTH / 64) * sizeof(double));
   switch (mk) {
     case MAP_LIN:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_LIN_DENS:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN_DENS, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_ACC_EM:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_EM, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
     case MAP_LANCZOS:   // fp64 only
       if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
+        hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LANCZOS, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
     default:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
+      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_MS, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
   }
+}
+
+template <typename T, int N>
+void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk, bool nt) {
+  if (nt) launch_xpass_r2c_t<T, N, true>(a, grid, st, mk);
+  else launch_xpass_r2c_t<T, N, false>(a, grid, st, mk);
 }
 
 template <typename T, int N, int RR = xpass_radix<T, N>()>
@@ -256,6 +265,7 @@ int p2_linec(int n, int prec, int D) {
 }
 
 struct Plan {
+  bool nt = false;   // real-mode x pass streams its own arrays nontemporally
   int dev = 0, d = 2, n[3] = {1, 1, 1}, prec = 0, nsolve = 1, symbol = 0;
   bool st = false;
   long long M = 0;
@@ -394,6 +404,16 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   // real mode: X holds half spectra, the real-space arrays hold real values
   const size_t xfield = real ? (size_t)nsolve * d * p->Mh * p->esz : field;
   const size_t rfield = real ? field / 2 : field;
+  // real mode: the x pass streams the phase map, E_prev and the H'' slots
+  // nontemporally when the half spectrum and E_prev alone exceed the 256 MB
+  // Infinity Cache (measured: 256^3 fp32 and fp64 gain; 2048^2 fp32 and fp64
+  // lose, the slots being touched only at phase-1 voxels; SCFFT_NT=0/1
+  // forces either)
+  {
+    const size_t foot = xfield + rfield;
+    const char* e = std::getenv("SCFFT_NT");
+    p->nt = real && (e ? std::atoi(e) != 0 : foot > kInfinityCacheBytes);
+  }
   auto fail = [&](hipError_t e) {
     free_plan(p);
     return e == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;
@@ -645,7 +665,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     rec(0);
     if (p->real) {
       const dim3 grid(p->xblocks, d, p->nsolve);
-#define C_(N) launch_xpass_r2c<T, N>(a, grid, st, p->mk)
+#define C_(N) launch_xpass_r2c<T, N>(a, grid, st, p->mk, p->nt)
       SCFFT_P2_SWITCH(p->n[0], C_)
 #undef C_
     } else if (p->p2x) {

@@ -264,6 +264,9 @@ def main() -> int:
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the headline iteration with per-kernel timing (for rocprofv3)")
+    ap.add_argument("--profile-workload", default="headline",
+                    choices=["headline", "cube256_acc_em_fp32", "square2048_acc_em_fp64"],
+                    help="workload of --profile-only")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3D cube, batched-sweep and gradient workloads")
     args = ap.parse_args()
@@ -296,9 +299,19 @@ def main() -> int:
         float(cal_x.sum())
         torch.cuda.synchronize()
         del cal_x
-        prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
-                                    alpha=0.25, beta=4.0, iters=args.profile_iters)
-        print(json.dumps({"profile": prof, "config": hs, "grid": [N, N]}), flush=True)
+        if args.profile_workload == "cube256_acc_em_fp32":
+            # 256^3 cube array, sigma1 = 100, the symmetrised power-iteration interval
+            chi3 = torch.as_tensor(inputs.cube_array(256)).cuda()
+            prof = scfft.profile_passes(chi3, 100.0, (1.0, 0.0, 0.0), "acc_em", precision="fp32",
+                                        alpha=0.1818, beta=5.5015, iters=args.profile_iters)
+            grid = [256, 256, 256]
+        else:
+            prec = "fp64" if args.profile_workload == "square2048_acc_em_fp64" else hs["precision"]
+            prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=prec,
+                                        alpha=0.25, beta=4.0, iters=args.profile_iters)
+            grid = [N, N]
+        print(json.dumps({"profile": prof, "workload": args.profile_workload, "grid": grid}),
+              flush=True)
         return 0
 
     # ---------------------------------------------------------- headline

@@ -80,6 +80,7 @@ struct XArgs {
   double invM;
   int ignore_done;
   int packed;           // real mode, 2D: rows of n0/2 values, column 0 = X(0) + i X(n0/2)
+  int hp;               // real mode: elements between consecutive rows of X (>= n0/2 + 1)
 };
 
 // Reduction inputs of the stop rules (see finalize_solve).
@@ -109,6 +110,7 @@ struct GArgs {
   int fin;              // 1: one extra workgroup per solve runs finalize_solve
   int packed;           // 2D real mode: column 0 holds kx = 0 (real part) and kx = n0/2 (imaginary)
   FArgs f;
+  int rp;               // elements between consecutive rows of X (the row pitch)
 };
 
 __device__ __forceinline__ void finalize_solve(const FArgs& a, int solve, int tid, int nth);
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(NT) void line_pass_kernel(GArgs a) {
   const int N = a.fd.n;
   const int x0 = blockIdx.x * C;
   const int nlc = min(C, a.n[0] - x0);
-  const long long off = x0 + (long long)blockIdx.y * a.n[0] * (gam ? 1 : a.n[1]);
+  const long long off = x0 + (long long)blockIdx.y * a.rp * (gam ? 1 : a.n[1]);
   // gam: 2D off = x0 (blockIdx.y = 0); 3D off = x0 + y*n0.  y pass: off = x0 + z*n0*n1.
   const long long M = a.M;
   cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M;

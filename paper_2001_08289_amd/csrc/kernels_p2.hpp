@@ -279,7 +279,7 @@ __global__ __launch_bounds__((LineShape<T, N, R, D, CW>::NTH)) void line_p2_kern
   // uniform 64-bit tile base + 32-bit per-lane element offsets
   const long long M = a.M;
   cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M + x0 +
-             (long long)by * a.n[0] * (gam ? 1 : a.n[1]);
+             (long long)by * a.rp * (gam ? 1 : a.n[1]);
   const unsigned int Mu = (unsigned int)M, su = (unsigned int)a.stride;
   const unsigned int lane_off = (unsigned int)c + (unsigned int)j * su;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);

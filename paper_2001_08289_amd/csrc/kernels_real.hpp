@@ -10,11 +10,13 @@
 //
 // Layout: real-space arrays (E_prev, S', T') are real [b][c][N^d]; the iterate
 // X is stored as the Hermitian half of its x-direction spectrum, kx = 0..n0/2.
-// In 3D a row holds H = n0/2 + 1 complex values ([b][c][H n1 n2]).  In 2D the
-// two coefficients that are real for a real row, kx = 0 and kx = n0/2, share
-// column 0 (real and imaginary part), so a row holds H = n0/2 values: the
-// Gamma pass then has n0/2 columns, which tile the machine without a lone
-// last tile.  Two real rows of one component share one complex FFT of length
+// In 3D a row holds H = n0/2 + 1 complex values.  In 2D (when that removes a
+// Gamma-pass tile from the busiest CU) the two coefficients that are real
+// for a real row, kx = 0 and kx = n0/2, share column 0 (real and imaginary
+// part), so a row holds H = n0/2 values.  Rows start every hp >= H elements
+// ([b][c][hp n1 n2]; the pad is never read); in 3D hp is a whole number of
+// 128-byte cache lines, so that a strided pass's tile of adjacent columns
+// shares cache lines only with the neighbouring tiles of the same row.  Two real rows of one component share one complex FFT of length
 // n0: w = a + i b, and a, b are recovered from w(k) and w(n0 - k).
 #pragma once
 
@@ -214,7 +216,6 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   using SH = XPassShape<N, R>;
   constexpr int TL = SH::TL, LINES = SH::LINES, NTH = SH::NTH;
   constexpr int LP = P2Plan<N, R>::LP;
-  const int H = a.packed ? N / 2 : N / 2 + 1;
   const int solve = blockIdx.z;
   const int comp = blockIdx.y;
   if (!a.ignore_done && a.ctl[solve].done) return;
@@ -227,8 +228,8 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_r2c_kernel(XArg
   const bool valid = pr < a.nlines / 2;
   const long long rowA = 2 * pr, rowB = 2 * pr + 1;
   const long long cbase = (long long)solve * a.d + comp;
-  cx<T>* XA = reinterpret_cast<cx<T>*>(a.X) + cbase * a.Mh + rowA * H;
-  cx<T>* XB = XA + H;
+  cx<T>* XA = reinterpret_cast<cx<T>*>(a.X) + cbase * a.Mh + rowA * a.hp;
+  cx<T>* XB = XA + a.hp;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   cx<T> v[R];
 #pragma unroll
@@ -348,7 +349,7 @@ struct InitRArgs {
   SolveCtl* ctl;
   const SolveCoef* coef;
   long long M, Mh;
-  int d, H, nsolve, has_st;
+  int d, H, nsolve, has_st;   // H: the row pitch of X
 };
 
 // X^0 = constant c per component: half spectrum M*c at kx = 0 of every row.

@@ -224,18 +224,22 @@ def test_autograd_function_matches_finite_differences():
     assert abs(fd - an) < 1e-6 * abs(an)
 
 
-@pytest.mark.parametrize("path", ["real", "real_packed", "real_nt", "complex", "generic"])
+@pytest.mark.parametrize("path", ["real", "real_packed", "real_nt", "real_padded", "real_unpadded",
+                                  "complex", "generic"])
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("shape", [(64, 128), (16, 32, 64)])
 def test_execution_paths_agree(path, scheme, shape, monkeypatch):
     """The real-field (half-spectrum; in 2D with or without kx = 0 and n0/2
     packed into one column; with the x pass's own arrays streamed
-    nontemporally or not), complex register-resident and generic LDS-staged
-    paths each match the oracle on the same case."""
+    nontemporally or not; rows of the half spectrum padded to cache lines or
+    not), complex register-resident and generic LDS-staged paths each match
+    the oracle on the same case."""
     if path == "real_packed" and len(shape) == 3:
         pytest.skip("the packed column is a 2D layout")
     monkeypatch.setenv("SCFFT_PACK", "1" if path == "real_packed" else "0")
     monkeypatch.setenv("SCFFT_NT", "1" if path == "real_nt" else "0")
+    if path in ("real_padded", "real_unpadded"):
+        monkeypatch.setenv("SCFFT_PITCH", "1" if path == "real_padded" else "0")
     if path not in ("real", "real_packed"):
         monkeypatch.setenv("SCFFT_NO_REAL", "1")
     if path == "generic":

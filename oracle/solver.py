@@ -55,16 +55,27 @@ class SolverArgError(ValueError):
 
 
 class GammaOperator:
-    """Gamma_1 on (d, *grid) real-space fields: FFT, per-mode symbol, inverse FFT."""
+    """Gamma_1 on (d, *grid) real-space fields: FFT, per-mode symbol, inverse FFT.
 
-    def __init__(self, grid_shape, symbol="rotated"):
+    fft = "own" uses the oracle's own FFT (pinned against numpy.fft and a
+    direct DFT); fft = "numpy" calls numpy.fft as a library step, for grids
+    (256^3) where the own FFT would take minutes.
+    """
+
+    def __init__(self, grid_shape, symbol="rotated", fft="own"):
         self.grid_shape = tuple(grid_shape)
         self.d = len(grid_shape)
         self.symbol = symbol
         self.vec = symbol_vectors(grid_shape, symbol)
         self.axes = tuple(range(1, self.d + 1))
+        if fft not in ("own", "numpy"):
+            raise ValueError(f"unknown fft {fft!r}")
+        self.fft = fft
 
     def __call__(self, x):
+        if self.fft == "numpy":
+            xh = np.fft.fftn(x, axes=self.axes)
+            return np.fft.ifftn(apply_gamma_hat(xh, self.vec, self.symbol), axes=self.axes)
         xh = fftn(x, self.axes)
         return ifftn(apply_gamma_hat(xh, self.vec, self.symbol), self.axes)
 
@@ -128,14 +139,14 @@ def _mean(x, d):
 
 def solve(chi, sigma1, e0, scheme="ms", alpha=None, beta=None, symbol="rotated",
           tol=1e-8, max_iter=500, sigma_field=None, sigma0=None,
-          stag_window=20, div_factor=1e3):
+          stag_window=20, div_factor=1e3, fft="own"):
     """Run one scheme to tolerance (or exactly max_iter iterates when tol < 0).
 
     Returns a dict with E, J (d, *grid), sigma_star, mean_J, iterations,
     residual, status, the histories and, for the H'' schemes, the slots of
     E'' and J'' (used by the embedding checks of eqs. J39-J40).
     stag_window = 0 disables the stagnation stop, div_factor = 0 the
-    divergence stop.
+    divergence stop.  fft selects the transform (see GammaOperator).
     """
     chi = np.asarray(chi)
     grid = chi.shape if sigma_field is None else np.asarray(sigma_field).shape
@@ -145,7 +156,7 @@ def solve(chi, sigma1, e0, scheme="ms", alpha=None, beta=None, symbol="rotated",
         raise SolverArgError(STATUS_INVALID_ARG, "bad dimension or zero e0")
     par = scheme_params(scheme, sigma1, alpha, beta, sigma_field, sigma0)
     sig = local_sigma(chi, sigma1, sigma_field)
-    gamma = GammaOperator(grid, symbol)
+    gamma = GammaOperator(grid, symbol, fft)
     e0f = e0.reshape((d,) + (1,) * d).astype(np.complex128)
     e0n2 = float(np.dot(e0, e0))
     ch = np.broadcast_to(chi.astype(np.float64), grid) if sigma_field is None else None
@@ -266,4 +277,15 @@ def solve(chi, sigma1, e0, scheme="ms", alpha=None, beta=None, symbol="rotated",
         out["slots_J"] = (E + ch[None] * (t - 1.0) * p1 * se,
                           ch[None] * (es + (t - 1.0) * p2 * se),
                           ch[None] * (et + (t - 1.0) * p3 * se))
+    elif scheme == "acc_ms":
+        # E'' = (E_Q, chi E_S, 0) and J'' = sigma'' E'' with
+        # sigma'' = I + (t - 1) chi p p^T (eq. J37)
+        p1, p2, p3 = par["p"]
+        t = par["t"]
+        es = ch[None] * state["S"]
+        se = p1 * E + p2 * es
+        out["slots_E"] = (E, es, np.zeros_like(E))
+        out["slots_J"] = (E + ch[None] * (t - 1.0) * p1 * se,
+                          ch[None] * (es + (t - 1.0) * p2 * se),
+                          ch[None] * (t - 1.0) * p3 * se)
     return out

@@ -4,17 +4,21 @@ The paper's projection onto curl-free zero-mean fields is
 Gamma_1 = k (x) k / |k|^2 for k != 0 and 0 at k = 0 (eq. J11, and eq. J45 for
 the Q-slot of H'').  The paper is continuum-only; on an N^d voxel grid the
 wavevector k is replaced by a discrete vector n(m) per DFT mode m.  Three
-readings are provided (theta_j = 2 pi m_j / n_j):
+readings are provided (theta_j = 2 pi m_j / n_j).  The periodic cell is the
+unit square (cube) and a voxel is 1/n_j wide along axis j, so each difference
+quotient carries the factor 1/h_j = n_j (on a grid with equal n_j the factor
+cancels in Gamma_1):
 
-  rotated   n_j = sin(theta_j/2) prod_{l != j} cos(theta_l/2)   (default);
-            modes with n = 0 but m != 0 (two or more Nyquist indices) use
-            n_j = [m_j == n_j/2];
-  spectral  the literal k of eq. J11: signed integer m_j in (-n/2, n/2];
-            at a mode with a Nyquist index and another non-zero non-Nyquist
-            index the Nyquist components are set to 0 (keeps real fields
-            real);
-  network   n_j = exp(i theta_j) - 1 (forward difference of the resistor
-            network of section 2), used as n (n^H . )/|n|^2.
+  rotated   n_j = n_j sin(theta_j/2) prod_{l != j} cos(theta_l/2)  (default;
+            the symbol of the difference across a voxel averaged over the
+            other axes); modes with n = 0 but m != 0 (two or more Nyquist
+            indices) use n_j = n_j [m_j == n_j/2];
+  spectral  the literal k of eq. J11 (up to the common factor 2 pi): signed
+            integer m_j in (-n/2, n/2]; at a mode with a Nyquist index and
+            another non-zero non-Nyquist index the Nyquist components are
+            set to 0 (keeps real fields real);
+  network   n_j = n_j (exp(i theta_j) - 1) (forward difference of the
+            resistor network of section 2), used as n (n^H . )/|n|^2.
 
 Layout: fields are (d, *grid) with grid shaped (n1, n0) or (n2, n1, n0);
 vector component c points along grid axis c, which is numpy axis d-1-c.
@@ -57,7 +61,7 @@ def symbol_vectors(grid_shape, symbol: str = "rotated") -> np.ndarray:
             c.append(cv)
         vec = np.zeros((d,) + full)
         for j in range(d):
-            v = s[j]
+            v = ns[j] * s[j]
             for l in range(d):
                 if l != j:
                     v = v * c[l]
@@ -69,7 +73,7 @@ def symbol_vectors(grid_shape, symbol: str = "rotated") -> np.ndarray:
         null = (norm2 == 0.0) & nonzero_mode
         if np.any(null):
             for j in range(d):
-                nyq = np.broadcast_to((2 * ms[j] == ns[j]).astype(float), full)
+                nyq = np.broadcast_to(ns[j] * (2 * ms[j] == ns[j]).astype(float), full)
                 vec[j] = np.where(null, nyq, vec[j])
         return vec
     if symbol == "spectral":
@@ -92,7 +96,7 @@ def symbol_vectors(grid_shape, symbol: str = "rotated") -> np.ndarray:
     if symbol == "network":
         vec = np.zeros((d,) + full, dtype=np.complex128)
         for j, (m, n) in enumerate(zip(ms, ns)):
-            vec[j] = np.broadcast_to(np.exp(2j * np.pi * m / n) - 1.0, full)
+            vec[j] = np.broadcast_to(n * (np.exp(2j * np.pi * m / n) - 1.0), full)
         return vec
     raise ValueError(f"unknown symbol {symbol!r}")
 

@@ -388,11 +388,12 @@ __device__ __forceinline__ T mode_symbol(const GArgs& a, const int* m, cx<T>* nv
       nrm += v * v;
     }
     if (nrm == (T)0) {
-      // n = 0 at m != 0 (two or more Nyquist indices): Nyquist-indicator direction
+      // n = 0 at m != 0 (two or more Nyquist indices): the Nyquist-indicator
+      // direction, scaled per axis (s[j] = n_j at a Nyquist index)
       for (int j = 0; j < d; ++j) {
-        const T v = (c[j] == (T)0) ? (T)1 : (T)0;
+        const T v = (c[j] == (T)0) ? s[j] : (T)0;
         nv[j] = mk<T>(v, 0);
-        nrm += v;
+        nrm += v * v;
       }
     }
     return nrm;
@@ -838,7 +839,7 @@ __global__ __launch_bounds__(256) void gradient_kernel(GradArgs a) {
   }
 }
 
-__global__ void sum_pairs_kernel(const double* part, int n, double* out) {
+static __global__ void sum_pairs_kernel(const double* part, int n, double* out) {
   __shared__ double red[2][256];
   double s0 = 0, s1 = 0;
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -872,11 +873,13 @@ __global__ void twiddle_kernel(cx<T>* tw, int n) {
   tw[k] = mk<T>((T)c, (T)-s);
 }
 
-// Per-axis symbol tables (double pairs):
-//   rotated : (sin(pi m/n), cos(pi m/n)) with the exact zeros at m = 0 / 2m = n
+// Per-axis symbol tables (double pairs).  The cell is the unit square
+// (cube): a voxel is 1/n wide along an axis of n voxels, so the difference
+// quotients carry the factor n.
+//   rotated : (n sin(pi m/n), cos(pi m/n)) with the exact zeros at m = 0 / 2m = n
 //   spectral: (signed m in (-n/2, n/2], 1 if 2m = n else 0)
-//   network : (cos(2 pi m/n) - 1, sin(2 pi m/n))
-__global__ void symbol_table_kernel(double* tab, int n, int symbol) {
+//   network : (n (cos(2 pi m/n) - 1), n sin(2 pi m/n))
+static __global__ void symbol_table_kernel(double* tab, int n, int symbol) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n) return;
   double a, b;
@@ -884,14 +887,15 @@ __global__ void symbol_table_kernel(double* tab, int n, int symbol) {
     sincospi((double)m / (double)n, &a, &b);
     if (m == 0) a = 0.0;
     if (2 * m == n) b = 0.0;
+    a *= (double)n;
   } else if (symbol == SYM_SPECTRAL) {
     a = (2 * m > n) ? (double)(m - n) : (double)m;
     b = (2 * m == n) ? 1.0 : 0.0;
   } else {
     double s, c;
     sincospi(2.0 * (double)m / (double)n, &s, &c);
-    a = c - 1.0;
-    b = s;
+    a = (double)n * (c - 1.0);
+    b = (double)n * s;
   }
   tab[2 * m] = a;
   tab[2 * m + 1] = b;

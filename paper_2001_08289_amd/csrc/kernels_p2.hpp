@@ -166,12 +166,13 @@ __device__ __forceinline__ T mode_symbol_t(int symbol, const T (*tv)[2], cx<T>* 
       nrm += v * v;
     }
     if (nrm == (T)0) {
-      // n = 0 at m != 0 (two or more Nyquist indices): Nyquist-indicator direction
+      // n = 0 at m != 0 (two or more Nyquist indices): the Nyquist-indicator
+      // direction, scaled per axis (s[q] = n_q at a Nyquist index)
 #pragma unroll
       for (int q = 0; q < D; ++q) {
-        const T v = (c[q] == (T)0) ? (T)1 : (T)0;
+        const T v = (c[q] == (T)0) ? s[q] : (T)0;
         nv[q] = mk<T>(v, 0);
-        nrm += v;
+        nrm += v * v;
       }
     }
     return nrm;

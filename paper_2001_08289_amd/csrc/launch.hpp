@@ -1,0 +1,65 @@
+// Launchers of the iteration passes.
+//
+// The kernels are templates over precision, line length, radix, tile width
+// and local map; their instantiations are split over several translation
+// units (launch_*.hip, each compiled once per precision) so that the library
+// builds in parallel.  The host driver (scfft.hip) calls only the functions
+// declared here.
+#pragma once
+
+#include "kernels_real.hpp"
+
+namespace scfft {
+
+// Register FFT radix per pass (measured on MI355X, fp32 and fp64): radix 4
+// (twice the threads per line, more waves in flight) wins for the x pass up
+// to n0 = 1024 (fp64: 2048) and for the 2D Gamma pass up to 1024; radix 8
+// (fewer LDS exchanges) wins for longer lines and for the 3D strided passes.
+template <typename T, int N>
+constexpr int xpass_radix() {
+  return (N <= 1024 || (sizeof(T) == 8 && N <= 2048)) ? 4 : 8;
+}
+template <typename T, int N, int D>
+constexpr int line_radix() {
+  return (D == 2 && N <= 1024) ? 4 : 8;
+}
+
+#define SCFFT_P2_SWITCH(n, CALL)  \
+  switch (n) {                    \
+    case 16: CALL(16); break;     \
+    case 32: CALL(32); break;     \
+    case 64: CALL(64); break;     \
+    case 128: CALL(128); break;   \
+    case 256: CALL(256); break;   \
+    case 512: CALL(512); break;   \
+    case 1024: CALL(1024); break; \
+    case 2048: CALL(2048); break; \
+    case 4096: CALL(4096); break; \
+    default: break;               \
+  }
+
+// Real-field x pass (power-of-two n0): local map `mk`, own streams
+// nontemporal when `nt`.  grid = (row-pair blocks, d, solves).
+template <typename T>
+void launch_xpass_real(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, bool nt);
+
+// Complex register-resident x pass (power-of-two n0).
+template <typename T>
+void launch_xpass_reg(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk);
+
+// Register-resident strided pass over lines of length n: D = 2 / 3 the Gamma
+// pass of a 2D / 3D grid (all components), D = 1 a plain 3D y pass; a.C is
+// the tile width (one of 1, 2, 4, 8; anything else the widest that fits).
+template <typename T, int D>
+void launch_line_reg(const GArgs& a, dim3 grid, hipStream_t st, int n);
+
+// fp64 Gamma pass of 2048-point columns with radix-16 register FFTs.
+void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
+
+// LDS-staged mixed-radix passes (any 2/3/5-smooth length).
+template <typename T>
+void launch_xpass_generic(const XArgs& a, dim3 grid, size_t lds, hipStream_t st);
+template <typename T>
+void launch_line_generic(const GArgs& a, dim3 grid, size_t lds, hipStream_t st);
+
+}  // namespace scfft

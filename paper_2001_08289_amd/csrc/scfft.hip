@@ -17,7 +17,7 @@
 #include <tuple>
 #include <vector>
 
-#include "kernels_real.hpp"
+#include "launch.hpp"
 #include "scfft.h"
 
 using cd = std::complex<double>;
@@ -74,104 +74,6 @@ constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
 bool is_p2(int n) { return n >= 16 && n <= 4096 && (n & (n - 1)) == 0; }
 
 
-// Register FFT radix per pass (measured on MI355X, fp32 and fp64): radix 4
-// (twice the threads per line, more waves in flight) wins for the x pass up
-// to n0 = 1024 (fp64: 2048) and for the 2D Gamma pass up to 1024; radix 8
-// (fewer LDS exchanges) wins for longer lines and for the 3D strided passes.
-template <typename T, int N>
-constexpr int xpass_radix() {
-  return (N <= 1024 || (sizeof(T) == 8 && N <= 2048)) ? 4 : 8;
-}
-template <typename T, int N, int D>
-constexpr int line_radix() {
-  return (D == 2 && N <= 1024) ? 4 : 8;
-}
-
-// --- register-resident launches, dispatched over the power-of-two sizes
-template <typename T, int N, bool NT, int RR = xpass_radix<T, N>()>
-void launch_xpass_r2c_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
-  using SH = XPassShape<N, RR>;
-  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
-                              (size_t)5 * (SH::NTH / 64) * sizeof(double));
-  switch (mk) {
-    case MAP_LIN:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN, NT>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_LIN_DENS:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LIN_DENS, NT>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_ACC_EM:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_EM, NT>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_LANCZOS:   // fp64 only
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LANCZOS, NT>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    default:
-      hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_MS, NT>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-  }
-}
-
-template <typename T, int N>
-void launch_xpass_r2c(const XArgs& a, dim3 grid, hipStream_t st, int mk, bool nt) {
-  if (nt) launch_xpass_r2c_t<T, N, true>(a, grid, st, mk);
-  else launch_xpass_r2c_t<T, N, false>(a, grid, st, mk);
-}
-
-template <typename T, int N, int RR = xpass_radix<T, N>()>
-void launch_xpass_p2(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
-  using SH = XPassShape<N, RR>;
-  const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
-                              (size_t)5 * (SH::NTH / 64) * sizeof(double));
-  switch (mk) {
-    case MAP_LIN:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LIN>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_LIN_DENS:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LIN_DENS>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_ACC_EM:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_LANCZOS:   // fp64 only
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    default:
-      hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-  }
-}
-
-template <typename T, int N, int D, int CW, int RR = line_radix<T, N, D>()>
-void launch_line_p2_cw(const GArgs& a, dim3 grid, hipStream_t st) {
-  using SH = LineShape<T, N, RR, D, CW>;
-  const size_t lds = (size_t)SH::LDS;
-  if (lds > 65536) {
-    // LDS beyond 64 KiB per workgroup (gfx950 has 160 KiB per CU) is opt-in
-    static size_t set = 0;
-    if (lds > set) {
-      (void)hipFuncSetAttribute((const void*)line_p2_kernel<T, N, RR, D, CW>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      set = lds;
-    }
-  }
-  hipLaunchKernelGGL((line_p2_kernel<T, N, RR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
-}
-
-// cw: tile width actually used (one of the instantiated widths).
-template <typename T, int N, int D>
-void launch_line_p2(const GArgs& a, dim3 grid, hipStream_t st) {
-  switch (a.C) {
-    case 1: launch_line_p2_cw<T, N, D, 1>(a, grid, st); break;
-    case 2: launch_line_p2_cw<T, N, D, 2>(a, grid, st); break;
-    case 4: launch_line_p2_cw<T, N, D, 4>(a, grid, st); break;
-    case 8: launch_line_p2_cw<T, N, D, 8>(a, grid, st); break;
-    default: launch_line_p2_cw<T, N, D, 0>(a, grid, st); break;
-  }
-}
-
 // 2D real mode: pack kx = 0 and kx = n0/2 into one column when that lowers
 // the number of Gamma-pass workgroups the busiest CU runs (the packed tile
 // does a little more work, so packing only pays where it removes a tile
@@ -202,19 +104,6 @@ int tuned_c(int cmax) {
   return cmax;
 }
 
-#define SCFFT_P2_SWITCH(n, CALL) \
-  switch (n) {                   \
-    case 16: CALL(16); break;    \
-    case 32: CALL(32); break;    \
-    case 64: CALL(64); break;    \
-    case 128: CALL(128); break;  \
-    case 256: CALL(256); break;  \
-    case 512: CALL(512); break;  \
-    case 1024: CALL(1024); break; \
-    case 2048: CALL(2048); break; \
-    case 4096: CALL(4096); break; \
-    default: break;              \
-  }
 
 // Radix 16 (2048 = 16*8*16, one LDS exchange fewer) measured faster only for
 // the fp64 Gamma pass of 2048^2 grids (115 -> 104 us), where it is the
@@ -645,7 +534,6 @@ void fill_ctl(SolveCtl& c, const scfft_options& o, int kind, int d, const double
 template <typename T>
 scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* density,
                                 hipStream_t st, bool ignore_done, hipEvent_t* ev) {
-  constexpr int EMAX = (sizeof(T) == 4 ? kElemsF32 : kElemsF64) / kNT;
   const int d = p->d;
   const size_t esz = sizeof(cx<T>);
   auto rec = [&](int k) {
@@ -676,21 +564,15 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     a.packed = p->packed ? 1 : 0;
     // the x pass reuses its LDS for a 5 x (kNT/64) fp64 reduction
     rec(0);
+    const dim3 grid(p->xblocks, d, p->nsolve);
     if (p->real) {
-      const dim3 grid(p->xblocks, d, p->nsolve);
-#define C_(N) launch_xpass_r2c<T, N>(a, grid, st, p->mk, p->nt)
-      SCFFT_P2_SWITCH(p->n[0], C_)
-#undef C_
+      launch_xpass_real<T>(a, grid, st, p->n[0], p->mk, p->nt);
     } else if (p->p2x) {
-      const dim3 grid(p->xblocks, d, p->nsolve);
-#define C_(N) launch_xpass_p2<T, N>(a, grid, st, p->mk)
-      SCFFT_P2_SWITCH(p->n[0], C_)
-#undef C_
+      launch_xpass_reg<T>(a, grid, st, p->n[0], p->mk);
     } else {
       const size_t lds =
           std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
-      hipLaunchKernelGGL((xpass_kernel<T, kNT, EMAX>), dim3(p->xblocks, d, p->nsolve), dim3(kNT),
-                         lds, st, a);
+      launch_xpass_generic<T>(a, grid, lds, st);
     }
     rec(1);
   }
@@ -732,12 +614,9 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(4);
     if (p->p2y) {
-#define C_(N) launch_line_p2<T, N, 1>(y, grid, st)
-      SCFFT_P2_SWITCH(p->n[1], C_)
-#undef C_
+      launch_line_reg<T, 1>(y, grid, st, p->n[1]);
     } else {
-      const size_t lds = (size_t)p->n[1] * p->yC * esz;
-      hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>), grid, dim3(kNT), lds, st, y);
+      launch_line_generic<T>(y, grid, (size_t)p->n[1] * p->yC * esz, st);
     }
     rec(5);
   }
@@ -754,27 +633,12 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     if ((p->r16g || p->p2g) && q.fin) grid.x += 1;   // the finalizing workgroups
     rec(6);
     if (p->r16g) {
-      if constexpr (sizeof(T) == 8) launch_line_p2_cw<T, 2048, 2, 0, 16>(q, grid, st);
+      if constexpr (sizeof(T) == 8) launch_line_r16_f64_2048(q, grid, st);
     } else if (p->p2g) {
-      if (d == 2) {
-#define C_(N) launch_line_p2<T, N, 2>(q, grid, st)
-        SCFFT_P2_SWITCH(nl, C_)
-#undef C_
-      } else {
-        switch (nl) {
-          case 16: launch_line_p2<T, 16, 3>(q, grid, st); break;
-          case 32: launch_line_p2<T, 32, 3>(q, grid, st); break;
-          case 64: launch_line_p2<T, 64, 3>(q, grid, st); break;
-          case 128: launch_line_p2<T, 128, 3>(q, grid, st); break;
-          case 256: launch_line_p2<T, 256, 3>(q, grid, st); break;
-          case 512: launch_line_p2<T, 512, 3>(q, grid, st); break;
-          case 1024: launch_line_p2<T, 1024, 3>(q, grid, st); break;
-          default: break;
-        }
-      }
+      if (d == 2) launch_line_reg<T, 2>(q, grid, st, nl);
+      else launch_line_reg<T, 3>(q, grid, st, nl);
     } else {
-      const size_t lds = (size_t)nl * d * p->gC * esz;
-      hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>), grid, dim3(kNT), lds, st, q);
+      launch_line_generic<T>(q, grid, (size_t)nl * d * p->gC * esz, st);
     }
     rec(7);
   }
@@ -788,12 +652,9 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     const dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(8);
     if (p->p2y) {
-#define C_(N) launch_line_p2<T, N, 1>(y, grid, st)
-      SCFFT_P2_SWITCH(p->n[1], C_)
-#undef C_
+      launch_line_reg<T, 1>(y, grid, st, p->n[1]);
     } else {
-      const size_t lds = (size_t)p->n[1] * p->yC * esz;
-      hipLaunchKernelGGL((line_pass_kernel<T, kNT, EMAX>), grid, dim3(kNT), lds, st, y);
+      launch_line_generic<T>(y, grid, (size_t)p->n[1] * p->yC * esz, st);
     }
     rec(9);
   }
@@ -976,28 +837,44 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
     if (rc != SCFFT_OK) return rc;
     if (ws != st) SCFFT_HIP(hipStreamSynchronize(st));
   }
-  hipGraphExec_t exec = nullptr;
+  // A chunk of ce iterations is one graph; where fewer than ce iterations
+  // remain before max_iter, single-iteration graphs are replayed instead, so
+  // no launch beyond the last possible iterate is queued.
+  hipGraphExec_t exec = nullptr, exec1 = nullptr;
   if (use_graph) {
-    scfft_status rc = get_graph(plans, phases, dens, ce, ws, &exec);
+    scfft_status rc = get_graph(plans, phases, dens, 1, ws, &exec1);
+    if (rc == SCFFT_OK && ce > 1 && max_iter + 1 >= ce)
+      rc = get_graph(plans, phases, dens, ce, ws, &exec);
     if (rc != SCFFT_OK) return rc;
   }
   hipEvent_t e0, e1;
   SCFFT_HIP(hipEventCreate(&e0));
   SCFFT_HIP(hipEventCreate(&e1));
   SCFFT_HIP(hipEventRecord(e0, ws));
+  // iterate n = 0..max_iter takes max_iter + 1 launches; a few spare chunks
+  // cover solves whose stop flag is set by the last of them
   const long long max_chunks = (long long)(max_iter + 1) / ce + 3;
+  const long long needed = (long long)max_iter + 1;
+  long long launched = 0;
   std::vector<std::vector<SolveCtl>> host(plans.size());
   bool all_done = false;
   for (long long chunk = 0; chunk < max_chunks && !all_done; ++chunk) {
-    if (exec) {
-      SCFFT_HIP(hipGraphLaunch(exec, ws));
+    const long long left = needed - launched;
+    const int k = (int)(left >= ce || left <= 0 ? ce : left);
+    if (use_graph) {
+      if (k == ce && exec) {
+        SCFFT_HIP(hipGraphLaunch(exec, ws));
+      } else {
+        for (int q = 0; q < k; ++q) SCFFT_HIP(hipGraphLaunch(exec1, ws));
+      }
     } else {
-      for (int k = 0; k < ce; ++k)
+      for (int q = 0; q < k; ++q)
         for (size_t i = 0; i < plans.size(); ++i) {
           scfft_status rc = launch_iteration(plans[i], phases[i], dens[i], ws);
           if (rc != SCFFT_OK) return rc;
         }
     }
+    launched += k;
     all_done = true;
     for (size_t i = 0; i < plans.size(); ++i) {
       host[i].resize(plans[i]->nsolve);

@@ -147,6 +147,27 @@ typedef struct {
 scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt,
                          scfft_result* res);
 
+/* Workspace of scfft_solve_noalloc per GPU, in bytes (160 MiB). */
+#define SCFFT_NOALLOC_BYTES (160u * 1024u * 1024u)
+
+/* scfft_solve for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, semantics and results as scfft_solve, but the call
+ * allocates and frees no device memory: its workspace (iterate, previous
+ * field, H'' slots, partial sums, control block, max_iter + 1 history
+ * entries, twiddle and symbol tables) lives in one fixed device array of
+ * SCFFT_NOALLOC_BYTES inside the library, one per GPU, held from the
+ * library's load until the process ends.  A problem whose workspace does
+ * not fit returns SCFFT_ERR_INVALID_ARG before any device work (2048^2 fp32
+ * with the accelerated scheme fits; 2048^2 fp64 and 256^3 do not).  Kernels
+ * are launched one by one on opt->stream (no graph replay).  Every call on
+ * one GPU uses that GPU's array and re-initialises what it reads; calls that
+ * overlap on one GPU (several host threads or streams) race, and the caller
+ * must serialise them.  The first call on a device also creates the two
+ * HIP events that time its loop. */
+scfft_status scfft_solve_noalloc(const scfft_problem* prob, const scfft_options* opt,
+                                 scfft_result* res);
+
 /* Batched sweep: nprob microstructures (grids may differ) times nsig
  * conductivities each.  sigma1s (host) holds nprob*nsig values, problem-major;
  * opts (host) holds one options struct per problem (alpha, beta may differ;

@@ -182,6 +182,7 @@ struct Plan {
   bool packed = false;                           // 2D real mode: kx = 0 and n0/2 share column 0
   int H = 0;                                     // stored x-spectrum length
   long long Mh = 0;                              // stored elements per component of X
+  size_t xbytes = 0, rbytes = 0;                 // X; each real-space array (E_prev, S, T)
 };
 
 int map_kind(int kind, bool density) {
@@ -235,19 +236,11 @@ scfft_status ensure_hist(Plan* p, int cap) {
   return SCFFT_OK;
 }
 
-// `slot` separates workspaces of same-shaped problems solved together.
-scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int symbol,
-                      hipStream_t stream, Plan** out, int slot = 0, bool real = false) {
-  int dev = 0;
-  SCFFT_HIP(hipGetDevice(&dev));
+// Every execution-path choice and buffer size of a plan (host only, no
+// device work besides reading the compute-unit count).
+void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, bool st, int symbol,
+                bool real) {
   const int n2 = d == 3 ? n[2] : 1;
-  PlanKey key{dev, d, n[0], n[1], n2, prec, nsolve, st, symbol, slot, real};
-  auto it = g_plans.find(key);
-  if (it != g_plans.end()) {
-    *out = it->second;
-    return SCFFT_OK;
-  }
-  Plan* p = new Plan();
   p->dev = dev;
   p->d = d;
   p->n[0] = n[0];
@@ -315,6 +308,44 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
     const char* e = std::getenv("SCFFT_NT");
     p->nt = real && (e ? std::atoi(e) != 0 : foot > kInfinityCacheBytes);
   }
+  p->xbytes = xfield;
+  p->rbytes = rfield;
+  for (int a = 0; a < d; ++a) p->fd[a] = make_desc(n[a]);
+}
+
+// Twiddle and symbol tables of every axis (into the plan's buffers).
+scfft_status plan_tables(Plan* p, hipStream_t stream) {
+  for (int a = 0; a < p->d; ++a) {
+    const int n = p->n[a];
+    const int blocks = (n + 255) / 256;
+    if (p->prec == SCFFT_FP32)
+      hipLaunchKernelGGL(twiddle_kernel<float>, dim3(blocks), dim3(256), 0, stream,
+                         reinterpret_cast<cx<float>*>(p->tw[a]), n);
+    else
+      hipLaunchKernelGGL(twiddle_kernel<double>, dim3(blocks), dim3(256), 0, stream,
+                         reinterpret_cast<cx<double>*>(p->tw[a]), n);
+    hipLaunchKernelGGL(symbol_table_kernel, dim3(blocks), dim3(256), 0, stream, p->sym[a], n,
+                       p->symbol);
+  }
+  SCFFT_HIP(hipGetLastError());
+  return SCFFT_OK;
+}
+
+// `slot` separates workspaces of same-shaped problems solved together.
+scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int symbol,
+                      hipStream_t stream, Plan** out, int slot = 0, bool real = false) {
+  int dev = 0;
+  SCFFT_HIP(hipGetDevice(&dev));
+  const int n2 = d == 3 ? n[2] : 1;
+  PlanKey key{dev, d, n[0], n[1], n2, prec, nsolve, st, symbol, slot, real};
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second;
+    return SCFFT_OK;
+  }
+  Plan* p = new Plan();
+  plan_shape(p, dev, d, n, prec, nsolve, st, symbol, real);
+  const size_t xfield = p->xbytes, rfield = p->rbytes;
   auto fail = [&](hipError_t e) {
     free_plan(p);
     return e == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;
@@ -331,20 +362,10 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
   if ((e = hipMalloc(&p->ctl, sizeof(SolveCtl) * nsolve)) != hipSuccess) return fail(e);
   if ((e = hipMalloc(&p->coef, sizeof(SolveCoef) * nsolve)) != hipSuccess) return fail(e);
   for (int a = 0; a < d; ++a) {
-    p->fd[a] = make_desc(n[a]);
     if ((e = hipMalloc(&p->tw[a], p->esz * n[a])) != hipSuccess) return fail(e);
     if ((e = hipMalloc(&p->sym[a], 2 * sizeof(double) * n[a])) != hipSuccess) return fail(e);
-    const int blocks = (n[a] + 255) / 256;
-    if (prec == SCFFT_FP32)
-      hipLaunchKernelGGL(twiddle_kernel<float>, dim3(blocks), dim3(256), 0, stream,
-                         reinterpret_cast<cx<float>*>(p->tw[a]), n[a]);
-    else
-      hipLaunchKernelGGL(twiddle_kernel<double>, dim3(blocks), dim3(256), 0, stream,
-                         reinterpret_cast<cx<double>*>(p->tw[a]), n[a]);
-    hipLaunchKernelGGL(symbol_table_kernel, dim3(blocks), dim3(256), 0, stream, p->sym[a], n[a],
-                       symbol);
-    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   }
+  if (plan_tables(p, stream) != SCFFT_OK) return fail(hipErrorLaunchFailure);
   if (ensure_hist(p, 64) != SCFFT_OK) {
     free_plan(p);
     return SCFFT_ERR_OOM;
@@ -828,9 +849,10 @@ scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const 
 // synchronise after their set-up copies).
 scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const uint8_t*>& phases,
                       const std::vector<const double*>& dens, int max_iter, int check_every,
-                      hipStream_t st, double* elapsed_ms) {
+                      hipStream_t st, double* elapsed_ms, bool allow_graph = true,
+                      hipEvent_t* timing = nullptr) {
   const int ce = std::max(1, check_every);
-  const bool use_graph = !std::getenv("SCFFT_NO_GRAPH");
+  const bool use_graph = allow_graph && !std::getenv("SCFFT_NO_GRAPH");
   hipStream_t ws = st;
   if (use_graph) {
     scfft_status rc = work_stream(st, &ws);
@@ -847,9 +869,15 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
       rc = get_graph(plans, phases, dens, ce, ws, &exec);
     if (rc != SCFFT_OK) return rc;
   }
+  // timing events: the caller's (created once) or made here
   hipEvent_t e0, e1;
-  SCFFT_HIP(hipEventCreate(&e0));
-  SCFFT_HIP(hipEventCreate(&e1));
+  if (timing) {
+    e0 = timing[0];
+    e1 = timing[1];
+  } else {
+    SCFFT_HIP(hipEventCreate(&e0));
+    SCFFT_HIP(hipEventCreate(&e1));
+  }
   SCFFT_HIP(hipEventRecord(e0, ws));
   // iterate n = 0..max_iter takes max_iter + 1 launches; a few spare chunks
   // cover solves whose stop flag is set by the last of them
@@ -894,8 +922,10 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
   float ms = 0;
   SCFFT_HIP(hipEventElapsedTime(&ms, e0, e1));
   if (elapsed_ms) *elapsed_ms = ms;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (!timing) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   if (!all_done) return SCFFT_ERR_DEVICE;   // the device never set its stop flag
   return SCFFT_OK;
 }
@@ -1731,6 +1761,124 @@ scfft_status scfft_profile_passes(const scfft_problem* prob, const scfft_options
   for (auto& e : ev) (void)hipEventDestroy(e);
   for (int k = 0; k < 5; ++k) ms[k] = acc_ms[k] / iters;
   return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------- allocation-free solve
+// scfft_solve_noalloc keeps its whole workspace in one file-scope device
+// array.  Each GPU holds its own copy from the library's load until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress reports for the current device (the array's name is a
+// host-side stand-in, not a device address).
+namespace scfft {
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)SCFFT_NOALLOC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchDev {
+  unsigned char* ptr = nullptr;   // this device's copy of `scratch`
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+std::map<int, ScratchDev> g_scratch;   // guarded by g_mutex
+
+// Set-up, once per device, with that device current.
+scfft_status scratch_for_device(int dev, ScratchDev** out) {
+  auto it = g_scratch.find(dev);
+  if (it == g_scratch.end()) {
+    ScratchDev sd;
+    void* ptr = nullptr;
+    SCFFT_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return SCFFT_ERR_DEVICE;
+    sd.ptr = static_cast<unsigned char*>(ptr);
+    SCFFT_HIP(hipEventCreate(&sd.ev[0]));
+    SCFFT_HIP(hipEventCreate(&sd.ev[1]));
+    it = g_scratch.emplace(dev, sd).first;
+  }
+  *out = &it->second;
+  return SCFFT_OK;
+}
+
+// Points the plan's buffers into the block at base (256-byte aligned
+// pieces); base == nullptr only sizes them.  Returns the bytes used.
+size_t carve(Plan* p, unsigned char* base, int hist_cap) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    off = (off + 255) / 256 * 256;
+    void* q = base ? static_cast<void*>(base + off) : nullptr;
+    off += bytes;
+    return q;
+  };
+  const size_t ns = (size_t)p->nsolve;
+  p->X = take(p->xbytes);
+  p->Ep = take(p->rbytes);
+  if (p->st) {
+    p->S = take(p->rbytes);
+    p->T = take(p->rbytes);
+  }
+  p->part = static_cast<double*>(take(sizeof(double) * 5 * ns * p->d * p->xblocks));
+  p->ctl = static_cast<SolveCtl*>(take(sizeof(SolveCtl) * ns));
+  p->coef = static_cast<SolveCoef*>(take(sizeof(SolveCoef) * ns));
+  p->hist_r = static_cast<double*>(take(sizeof(double) * (size_t)hist_cap * ns));
+  p->hist_s = static_cast<double*>(take(2 * sizeof(double) * (size_t)hist_cap * ns));
+  p->hist_cap = hist_cap;
+  for (int a = 0; a < p->d; ++a) {
+    p->tw[a] = take(p->esz * p->n[a]);
+    p->sym[a] = static_cast<double*>(take(2 * sizeof(double) * p->n[a]));
+  }
+  return off;
+}
+
+}  // namespace
+}  // namespace scfft
+
+extern "C" {
+
+scfft_status scfft_solve_noalloc(const scfft_problem* prob, const scfft_options* opt,
+                                 scfft_result* res) {
+  if (!res) return SCFFT_ERR_INVALID_ARG;
+  if (!prob) return SCFFT_ERR_INVALID_ARG;
+  SolveSpec sp{};
+  scfft_status rc = prepare(prob, opt, cd(prob->sigma1.re, prob->sigma1.im), &sp);
+  if (rc != SCFFT_OK) {
+    res->status = rc;
+    return rc;
+  }
+  if (prob->density && !opt->sigma0_set) sp.s0 = graded_sigma0(opt->scheme, sp.s1);
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
+  int dev = 0;
+  SCFFT_HIP(hipGetDevice(&dev));
+  ScratchDev* sd = nullptr;
+  rc = scratch_for_device(dev, &sd);
+  if (rc != SCFFT_OK) return rc;
+  Plan p;
+  const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
+  plan_shape(&p, dev, prob->d, prob->n, opt->precision, 1, acc, opt->symbol,
+             real_ok(sp, prob->d, prob->n));
+  const int cap = opt->max_iter + 1;
+  if (carve(&p, nullptr, cap) > kScratchBytes) {
+    res->status = SCFFT_ERR_INVALID_ARG;
+    return SCFFT_ERR_INVALID_ARG;
+  }
+  carve(&p, sd->ptr, cap);
+  rc = plan_tables(&p, st);
+  if (rc != SCFFT_OK) return rc;
+  SolveCtl c;
+  SolveCoef cf;
+  fill_ctl(c, *opt, sp.kind, prob->d, prob->e0);
+  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p.M);
+  p.mk = map_kind(sp.kind, prob->density != nullptr);
+  SCFFT_HIP(hipMemcpyAsync(p.ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  SCFFT_HIP(hipMemcpyAsync(p.coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
+  rc = launch_init(&p, st);
+  if (rc != SCFFT_OK) return rc;
+  double ms = 0;
+  rc = run_loop({&p}, {prob->phase}, {prob->density}, opt->max_iter, opt->check_every, st, &ms,
+                false, sd->ev);
+  if (rc != SCFFT_OK) return rc;
+  return read_result(&p, 0, prob, res, st, ms);
 }
 
 }  // extern "C"

@@ -59,7 +59,8 @@ class Result(ctypes.Structure):
                 ("elapsed_ms", ctypes.c_double)]
 
 
-EXPORTS = ("scfft_default_options", "scfft_solve", "scfft_solve_batch", "scfft_estimate_interval",
+EXPORTS = ("scfft_default_options", "scfft_solve", "scfft_solve_noalloc", "scfft_solve_batch",
+           "scfft_estimate_interval",
            "scfft_gradient", "scfft_effective_tensor", "scfft_series_coefficients",
            "scfft_series_evaluate", "scfft_lanczos", "scfft_estimate_interval_lanczos",
            "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
@@ -76,6 +77,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.scfft_default_options.restype = None
     lib.scfft_solve.argtypes = [P, O, R]
     lib.scfft_solve.restype = ctypes.c_int
+    lib.scfft_solve_noalloc.argtypes = [P, O, R]
+    lib.scfft_solve_noalloc.restype = ctypes.c_int
     lib.scfft_solve_batch.argtypes = [ctypes.c_int, P, O, ctypes.c_int, ctypes.POINTER(c64), R]
     lib.scfft_solve_batch.restype = ctypes.c_int
     lib.scfft_estimate_interval.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -235,8 +238,9 @@ def _result_dict(res: Result, d: int, E=None, J=None, hist_r=None, hist_s=None) 
 def solve(phase=None, sigma1=1.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,
           precision="fp64", symbol="rotated", alpha=0.25, beta=4.0, tol=1e-8, max_iter=1000,
           check_every=16, stag_window=20, div_factor=1e3, sigma0=None, fields=True,
-          history=True, raise_on_error=True, stream=None) -> dict:
-    """Run scfft_solve.  E and J come back as complex128 CUDA tensors (d, *grid)."""
+          history=True, raise_on_error=True, stream=None, noalloc=False) -> dict:
+    """Run scfft_solve (scfft_solve_noalloc when noalloc is set).  E and J come
+    back as complex128 CUDA tensors (d, *grid)."""
     torch = _torch()
     prob, keep = make_problem(phase, density, sigma1, e0)
     opt = make_options(scheme, precision, symbol, alpha, beta, tol, max_iter, check_every,
@@ -257,9 +261,10 @@ def solve(phase=None, sigma1=1.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, densit
         res.residual_history = hist_r.ctypes.data
         res.sigma_history = hist_s.ctypes.data
         res.history_cap = cap
-    rc = _lib.scfft_solve(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
+    fn = _lib.scfft_solve_noalloc if noalloc else _lib.scfft_solve
+    rc = fn(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(res))
     if rc in (ERR_INVALID_ARG, ERR_SLIT, ERR_DEVICE, ERR_OOM) and raise_on_error:
-        raise ScfftError(rc, "scfft_solve")
+        raise ScfftError(rc, "scfft_solve_noalloc" if noalloc else "scfft_solve")
     return _result_dict(res, d, E, J, hist_r, hist_s)
 
 

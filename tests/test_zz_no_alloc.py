@@ -1,0 +1,69 @@
+"""scfft_solve_noalloc (workspace in the library's fixed device array)
+against scfft_solve (cached workspaces) through the C ABI: the same kernels
+on the same inputs give the same iterates, so results agree to rounding;
+two calls in a row, the second on a smaller problem, reuse the array."""
+import numpy as np
+import pytest
+
+from paper_2001_08289_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2001_08289_amd import scfft  # noqa: E402
+
+CASES = [
+    # (map, sigma1, e0, scheme, precision, tol, max_iter)
+    (lambda: inputs.square_array(2048), 100.0, (1, 0), "acc_em", "fp32", 1e-6, 60),
+    (lambda: inputs.random_phase((96, 80), 0.3, seed=5), 3 + 2j, (1, 0.5), "ms", "fp64", 1e-10, 300),
+    (lambda: inputs.random_phase((16, 24, 32), 0.3, seed=6), 10.0, (0, 0, 1), "acc_em", "fp64",
+     -1, 7),
+    (lambda: inputs.random_disks(288, seed=3)[0], 50.0, (1, 0), "em", "fp32", 1e-6, 400),
+]
+
+
+def _pair(case):
+    make, s1, e0, scheme, precision, tol, max_iter = case
+    chi = torch.as_tensor(make()).cuda()
+    kw = dict(alpha=0.25, beta=4.0, precision=precision, tol=tol, max_iter=max_iter,
+              stag_window=0 if tol < 0 else 20, div_factor=0 if tol < 0 else 1e3)
+    ref = scfft.solve(chi, s1, e0, scheme, **kw)
+    got = scfft.solve(chi, s1, e0, scheme, noalloc=True, **kw)
+    return ref, got
+
+
+def _check(ref, got):
+    assert got["status"] == ref["status"]
+    assert got["iterations"] == ref["iterations"]
+    assert abs(got["sigma_star"] - ref["sigma_star"]) <= 1e-13 * abs(ref["sigma_star"])
+    scale = ref["E"].abs().max().item()
+    assert (got["E"] - ref["E"]).abs().max().item() <= 1e-13 * scale
+    assert (got["J"] - ref["J"]).abs().max().item() <= 1e-13 * ref["J"].abs().max().item()
+    n = ref["iterations"]
+    assert np.array_equal(np.isnan(got["residual_history"]), np.isnan(ref["residual_history"]))
+    ok = ~np.isnan(ref["residual_history"])
+    assert np.allclose(got["residual_history"][ok], ref["residual_history"][ok], rtol=1e-12,
+                       atol=0)
+    assert len(got["sigma_history"]) == n + 1
+
+
+@pytest.mark.parametrize("order", [(0, 1), (2, 3), (0, 2)])
+def test_noalloc_matches_solve_two_calls(order):
+    """Two calls in a row, the second on a smaller problem."""
+    for k in order:
+        ref, got = _pair(CASES[k])
+        _check(ref, got)
+        del ref, got
+
+
+def test_noalloc_rejects_problems_beyond_its_array():
+    chi = torch.as_tensor(inputs.square_array(2048)).cuda()
+    with pytest.raises(scfft.ScfftError) as e:
+        scfft.solve(chi, 100.0, (1, 0), "acc_em", precision="fp64", noalloc=True)
+    assert e.value.status == scfft.ERR_INVALID_ARG
+    # the array still serves a fitting problem afterwards
+    ref, got = _pair(CASES[1])
+    _check(ref, got)

@@ -196,31 +196,36 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters,
  * sigma*(sigma1) (section "Estimating the parameters alpha and beta": the
  * singularities sit at sigma1 = 1 - 1/mu, mu in the support of the measure
  * of A = Gamma_1 chi Gamma_1 on E with respect to v_0 = Gamma_1 chi e0).
- * fp64 on the device: the unnormalised recurrence
- *   w_0 = v_0,  w_j = A w_{j-1} - a_{j-1} w_{j-1} - gamma_{j-1} w_{j-2},
- *   a_j = (w_j, chi w_j)/(w_j, w_j),  gamma_j = |w_j|^2/|w_{j-1}|^2,
- * one x pass and one Gamma pass per step, without reorthogonalisation.
- * prob->phase and prob->e0 (non-zero) are used; 1 <= steps <= 200.
- * a (host, steps entries) receives a_0..a_{m-1}, b (host, steps entries)
- * receives b_j = sqrt(gamma_j), j = 1..m-1, in b[0..m-2]; norm0 = |v_0|^2
- * (sum over voxels); m = number of steps completed (fewer than steps when the
- * Krylov space closes, i.e. |w_j| vanishes).  The Gauss rule of the
- * tridiagonal matrix (a, b) gives the nodes mu_i and weights
- * norm0 * (first eigenvector component)^2. */
+ * fp64 on the device with full reorthogonalisation:
+ *   q_0 = v_0/|v_0|,  r = A q_j minus its components along q_0..q_j
+ *   (classical Gram-Schmidt, twice), a_j = the component removed along q_j,
+ *   b_{j+1} = |r|, q_{j+1} = r/b_{j+1};
+ * one x pass and one Gamma pass per step; the steps + 1 basis vectors are
+ * held in a device buffer allocated for the call.  prob->phase and prob->e0
+ * (non-zero) are used; 1 <= steps <= 200.  a (host, steps entries) receives
+ * a_0..a_{m-1}, b (host, steps entries) receives b_1..b_{m-1} in
+ * b[0..m-2] and b_m, the norm of the last residual (0 when the space
+ * closed), in b[m-1]; norm0 = |v_0|^2 (sum over voxels); m = number of
+ * steps completed (fewer than steps when b_{j+1} < 1e-12 max(1, |a_j|), i.e.
+ * the Krylov space closed).  The Gauss rule of the tridiagonal matrix
+ * (a_0..a_{m-1}, b_1..b_{m-1}) gives the nodes mu_i and weights
+ * norm0 * (first eigenvector component)^2; node i lies within
+ * b_m |last eigenvector component| of an eigenvalue of A.
+ * SCFFT_ERR_INVALID_ARG when v_0 = 0 (e0 sees no inhomogeneity). */
 scfft_status scfft_lanczos(const scfft_problem* prob, int steps, int symbol,
                            void* stream, double* a, double* b, double* norm0,
                            int* m);
 
 /* Interval [alpha, beta] from the Lanczos Gauss rule (host Jacobi
  * eigen-decomposition of the tridiagonal matrix): mu_min / mu_max are the
- * extreme nodes whose weight exceeds rel_weight times the total and which
- * pass the Cullum-Willoughby test (a simple node that is also an eigenvalue
- * of the matrix without its first row and column, within 1e-8, comes from
- * rounding and is dropped), alpha = 1/mu_max - 1,
- * beta = 1/mu_min - 1, and the interval for the accelerated scheme follows
- * the floating-point stability rule alpha_used = min(alpha, 1/beta),
- * beta_used = 1/alpha_used (every output pointer may be NULL).
- * SCFFT_ERR_INVALID_ARG when no node lies inside (0, 1). */
+ * extreme nodes whose weight exceeds rel_weight times the total (1e-20
+ * separates the measure from rounding: with full reorthogonalisation,
+ * nodes the measure does not support carry weights of order 1e-32),
+ * alpha = 1/mu_max - 1, beta = 1/mu_min - 1, and the interval for the
+ * accelerated scheme follows the floating-point stability rule
+ * alpha_used = min(alpha, 1/beta), beta_used = 1/alpha_used (every output
+ * pointer may be NULL).  SCFFT_ERR_INVALID_ARG when no node lies inside
+ * (0, 1). */
 scfft_status scfft_estimate_interval_lanczos(const scfft_problem* prob, int steps,
                                              int symbol, void* stream,
                                              double rel_weight, double* alpha,

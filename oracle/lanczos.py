@@ -19,10 +19,20 @@ The eigenvalues theta_i of the tridiagonal matrix T (diagonal a, off-diagonal
 b) are the Gauss nodes of the measure; the squared first components of its
 eigenvectors, times |v_0|^2, are the Gauss weights.  Then
     alpha = 1/mu_max - 1,   beta = 1/mu_min - 1
-from the extreme nodes whose weight is not negligible and which pass the
-Cullum-Willoughby test for spurious nodes (needed by a recurrence without
-reorthogonalisation; harmless here), and the interval actually used follows the floating-point stability rule of the accelerated
-scheme: alpha_u = min(alpha, 1/beta), beta_u = 1/alpha_u.
+from the extreme nodes whose relative weight exceeds rel_weight = 1e-20,
+and the interval actually used follows the floating-point stability rule of
+the accelerated scheme: alpha_u = min(alpha, 1/beta), beta_u = 1/alpha_u.
+
+The cut-off separates the measure of v_0 from rounding.  With full
+reorthogonalisation the Lanczos vectors are orthonormal to fp64 rounding
+(eps ~ 1e-16), so a Ritz vector that the measure does not support still
+overlaps v_0 by O(eps) and its Gauss weight is O(eps^2) ~ 1e-32 of the total
+(such nodes appear once the Krylov space is exhausted, typically at mu ~ 0
+and mu ~ 1, the zero-weight eigenspaces of fields supported in one phase).
+A node of weight w of the measure itself is resolved as long as w is far
+above that level, so the threshold sits at 1e-20, twelve orders above
+rounding and below any weight the tests' maps produce (pinned against a
+dense eigen-decomposition with an extreme node of relative weight ~1e-10).
 """
 from __future__ import annotations
 
@@ -31,9 +41,12 @@ import numpy as np
 from .solver import GammaOperator
 
 
-def lanczos(chi, e0, steps: int, symbol="rotated"):
+def lanczos(chi, e0, steps: int, symbol="rotated", residual=False):
     """Coefficients (a_0..a_{m-1}, b_1..b_{m-1}) and |v_0|^2; m <= steps
-    (fewer if the Krylov space closes)."""
+    (fewer if the Krylov space closes).  With residual=True also b_m, the
+    norm of the last residual (0 when the space closed): a Ritz value theta_i
+    lies within b_m |s_{m,i}| of an eigenvalue of A (s_i its eigenvector of
+    the tridiagonal matrix)."""
     chi = np.asarray(chi)
     d = chi.ndim
     gamma = GammaOperator(chi.shape, symbol)
@@ -58,7 +71,17 @@ def lanczos(chi, e0, steps: int, symbol="rotated"):
             break
         b.append(bj)
         Qs.append(r / bj)
+    if residual:
+        return np.array(a), np.array(b), n0, (bj if j == steps - 1 else 0.0)
     return np.array(a), np.array(b), n0
+
+
+def ritz_bounds(a, b, b_last):
+    """Residual bound b_m |s_{m,i}| of every Gauss node (same order as
+    gauss_rule's nodes)."""
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    _, vec = np.linalg.eigh(T)
+    return b_last * np.abs(vec[-1])
 
 
 def gauss_rule(a, b, n0: float = 1.0):
@@ -68,32 +91,19 @@ def gauss_rule(a, b, n0: float = 1.0):
     return theta, n0 * vec[0] ** 2
 
 
-def spurious(a, b, tol: float = 1e-8):
-    """Cullum-Willoughby test: a simple eigenvalue of T that is also an
-    eigenvalue of T with its first row and column removed (within tol) does
-    not belong to the measure of v_0 (it is produced by rounding once the
-    Lanczos vectors lose orthogonality); numerically multiple eigenvalues
-    are copies of converged ones and are kept."""
-    theta, _ = gauss_rule(a, b)
-    if len(a) < 2:
-        return np.zeros(len(theta), dtype=bool)
-    that = np.linalg.eigvalsh(np.diag(a[1:]) + np.diag(b[1:], 1) + np.diag(b[1:], -1))
-    out = np.zeros(len(theta), dtype=bool)
-    for i, t in enumerate(theta):
-        multiple = np.sum(np.abs(theta - t) < 1e-8) >= 2
-        out[i] = (not multiple) and np.min(np.abs(that - t)) < tol
-    return out
+REL_WEIGHT = 1e-20
 
 
-def support_estimate(a, b, n0: float = 1.0, rel_weight: float = 1e-6):
-    """(mu_min, mu_max): extreme Gauss nodes that pass the Cullum-Willoughby
-    test and whose weight exceeds rel_weight times the total weight."""
+def support_estimate(a, b, n0: float = 1.0, rel_weight: float = REL_WEIGHT):
+    """(mu_min, mu_max): extreme Gauss nodes whose weight exceeds rel_weight
+    times the total weight."""
     theta, wts = gauss_rule(a, b, n0)
-    keep = (wts > rel_weight * wts.sum()) & ~spurious(a, b)
+    keep = wts > rel_weight * wts.sum()
     return float(theta[keep].min()), float(theta[keep].max())
 
 
-def interval(chi, e0=(1.0, 0.0, 0.0), steps: int = 60, symbol="rotated", rel_weight: float = 1e-6):
+def interval(chi, e0=(1.0, 0.0, 0.0), steps: int = 60, symbol="rotated",
+             rel_weight: float = REL_WEIGHT):
     """(alpha, beta, alpha_u, beta_u, mu_min, mu_max)."""
     a, b, n0 = lanczos(chi, e0, steps, symbol)
     mu_min, mu_max = support_estimate(a, b, n0, rel_weight)

@@ -22,7 +22,7 @@
 
 namespace scfft {
 
-enum Kind { K_MS = 0, K_EM = 1, K_ACC_EM = 2, K_ACC_MS = 3, K_POWER = 4, K_ADJ = 5, K_LANCZOS = 6 };
+enum Kind { K_MS = 0, K_EM = 1, K_ACC_EM = 2, K_ACC_MS = 3, K_POWER = 4, K_ADJ = 5 };
 enum Sym { SYM_ROTATED = 0, SYM_SPECTRAL = 1, SYM_NETWORK = 2 };
 
 // Per-solve control block (device resident).  The host writes the parameter
@@ -37,8 +37,6 @@ struct SolveCtl {
   int iter, done, status, since_min;
   double min_r, res, sstar_re, sstar_im, lam;
   double meanJ[6];
-  // Lanczos recurrence (K_LANCZOS): a_{j}, gamma_{j} = |w_j|^2/|w_{j-1}|^2, |w_j|^2
-  double lz_a, lz_g, lz_n2;
 };
 
 // Per-solve coefficients of the local real-space map (device resident).
@@ -142,8 +140,7 @@ __device__ __forceinline__ void acc_settle(Acc& acc) {
 // forward FFT receives: MS tau = (1 - sigma/sigma0) E; EM R = Z P; H'' the
 // Q-slot of Z'' P'' (eq. J36 form) or of (I - sigma''/sigma0'') E''; the
 // power and adjoint kinds their own linear maps.
-enum MapKind { MAP_LIN = 0, MAP_LIN_DENS = 1, MAP_ACC_EM = 2, MAP_ACC_MS = 3, MAP_ANY = 4,
-               MAP_LANCZOS = 5 };
+enum MapKind { MAP_LIN = 0, MAP_LIN_DENS = 1, MAP_ACC_EM = 2, MAP_ACC_MS = 3, MAP_ANY = 4 };
 
 // MK fixes the branch at compile time (MAP_ANY decides at run time).
 template <typename T, int MK = MAP_ANY>
@@ -152,7 +149,6 @@ struct LocalMap {
   cx<T> cE[2], cO[2], cJ[2], cS[2];
   cx<T> s1, s0, p1, p2, p3, z, inv1w, p1kap;
   T invM, e0c;
-  T la, lg;   // Lanczos: a_{j-1}, gamma_{j-1}
   const uint8_t* phase;
   const double* dens;
   cx<T>* S;
@@ -181,8 +177,6 @@ struct LocalMap {
     p1kap = ld2<T>(cf.p1kap);
     invM = (T)a.invM;
     e0c = (T)ctl.e0[comp];
-    la = (T)ctl.lz_a;
-    lg = (T)ctl.lz_g;
     phase = a.phase;
     dens = a.density;
     S = a.Sslot ? reinterpret_cast<cx<T>*>(a.Sslot) + fbase : nullptr;
@@ -206,28 +200,6 @@ struct LocalMap {
                                               Acc& acc) const {
     const cx<T> x = invM * raw;
     cx<T> E, J, out;
-    const bool lz = MK == MAP_ANY ? kind == K_LANCZOS : MK == MAP_LANCZOS;
-    if (lz) {
-      // Lanczos on Gamma_1 chi Gamma_1: x = A w_{j-1}; w_j = x - a w_{j-1} - gamma w_{j-2}
-      // (S holds w_{j-2}, E_prev w_{j-1}); the FFT receives chi w_j.  Iterate 0
-      // only forms the start vector Gamma_1 chi e0 and clears both slots.
-      cx<T> w = x;
-      if (iter == 0) {
-        S[g] = mk<T>(0, 0);
-        Ep[g] = mk<T>(0, 0);
-      } else {
-        const cx<T> w1 = Ep[g], w2 = S[g];
-        w = x - la * w1 - lg * w2;
-        S[g] = w1;
-        Ep[g] = w;
-      }
-      const cx<T> cw = phase[g] ? w : mk<T>(0, 0);
-      acc.Jr += (double)cw.x;
-      acc.Ji += (double)cw.y;
-      acc.e2 += (double)norm2(w);
-      acc.eJ += (double)norm2(cw);
-      return cw;
-    }
     const bool acc_kind = MK == MAP_ANY ? (kind == K_ACC_EM || kind == K_ACC_MS)
                                         : (MK == MAP_ACC_EM || MK == MAP_ACC_MS);
     const bool acc_em = MK == MAP_ANY ? kind == K_ACC_EM : MK == MAP_ACC_EM;
@@ -534,33 +506,6 @@ __device__ __forceinline__ void finalize_status(const FArgs& a, SolveCtl* ctl, c
   si *= ctl->inv_e0n2;
   const double e2 = tot[6], d2 = tot[7], eJ = tot[8];
   const double lam = eJ / e2;
-  if (ctl->kind == K_LANCZOS) {
-    // iterate n >= 1 reduced w_{n-1}: a = (w, chi w)/(w, w), gamma = |w|^2/|w_prev|^2
-    double la = 0, lg = 0;
-    if (n >= 1) {
-      la = eJ / e2;
-      lg = (n >= 2) ? e2 / ctl->lz_n2 : 0.0;
-    }
-    if (n < a.hist_cap) {
-      a.hist_r[(long long)solve * a.hist_cap + n] = lg;
-      a.hist_s[((long long)solve * a.hist_cap + n) * 2] = la;
-      a.hist_s[((long long)solve * a.hist_cap + n) * 2 + 1] = n >= 1 ? e2 : 0.0;
-    }
-    ctl->lz_a = la;
-    ctl->lz_g = lg;
-    ctl->lz_n2 = n >= 1 ? e2 : 0.0;
-    // |w_j| below 1e-12 |w_{j-1}| (the Krylov space closed: w_j is rounding)
-    // or a non-finite value ends the process; iterate n then does not count
-    const bool brk = n >= 1 && !(e2 > 0 && isfinite(e2) && isfinite(la) && isfinite(lg) &&
-                                 (n < 2 || lg > 1e-24));
-    if (brk || n >= ctl->max_iter) {
-      ctl->status = brk ? -4 : -3;
-      ctl->done = 1;
-    } else {
-      ctl->iter = n + 1;
-    }
-    return;
-  }
   double r = __builtin_nan("");
   if (n >= 1) r = (e2 > 0) ? sqrt(d2 / e2) : __builtin_inf();
   if (n < a.hist_cap) {

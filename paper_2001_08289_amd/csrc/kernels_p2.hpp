@@ -89,7 +89,7 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_p2_kernel(XArgs
     for (int i = 0; i < R; ++i) {
       const long long g = base + j + TL * i;
       v[i] = PF ? lm.apply_pf(v[i], g, ph[i], epo[i], acc) : lm.apply(v[i], g, acc);
-      if (MK != MAP_LANCZOS) acc_settle<true>(acc);
+      acc_settle<true>(acc);
     }
   }
   reg_fft<T, N, R>(v, slot, j, (T)-1, tw);

@@ -47,7 +47,6 @@ struct LocalMapR {
   T cE[2], cO[2], cJ[2], cS[2];
   T s1, s0, p1, q2, q3, z, inv1w, p1kap;
   T invM, e0c;
-  T la, lg;   // Lanczos: a_{j-1}, gamma_{j-1}
   const uint8_t* phase;
   const double* dens;
   T* S;
@@ -75,8 +74,6 @@ struct LocalMapR {
     p1kap = (T)cf.p1kap[0];
     invM = (T)a.invM;
     e0c = (T)ctl.e0[comp];
-    la = (T)ctl.lz_a;
-    lg = (T)ctl.lz_g;
     phase = a.phase;
     dens = a.density;
     S = a.Sslot ? reinterpret_cast<T*>(a.Sslot) + rbase : nullptr;
@@ -103,27 +100,7 @@ struct LocalMapR {
     return w;
   }
 
-  // Lanczos step (see LocalMap): S holds w_{j-2}, E_prev w_{j-1}
-  __device__ __forceinline__ T lanczos(T x, bool ph, T& sref, T& eref, Acc& acc) const {
-    T v = x;
-    if (iter == 0) {
-      sref = (T)0;
-      eref = (T)0;
-    } else {
-      const T w1 = eref, w2 = sref;
-      v = x - la * w1 - lg * w2;
-      sref = w1;
-      eref = v;
-    }
-    const T cw = ph ? v : (T)0;
-    acc.Jr += (double)cw;
-    acc.e2 += (double)(v * v);
-    acc.eJ += (double)(cw * cw);
-    return cw;
-  }
-
   __device__ __forceinline__ T apply(T raw, const Row& w, unsigned int k, Acc& acc) const {
-    if (MK == MAP_LANCZOS) return lanczos(invM * raw, w.ph[k] != 0, w.S[k], w.Ep[k], acc);
     const bool ph = MK == MAP_LIN_DENS ? false : w.ph[k] != 0;
     return apply_pf<false>(raw, ph, w.Ep[k], (T)0, (T)0, w, k, acc);
   }

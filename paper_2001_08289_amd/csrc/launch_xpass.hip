@@ -24,10 +24,6 @@ void xreal_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
     case MAP_ACC_EM:
       hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_EM, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
-    case MAP_LANCZOS:   // fp64 only
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_LANCZOS, NT>), grid, dim3(SH::NTH), lds, st, a);
-      break;
     default:
       hipLaunchKernelGGL((xpass_r2c_kernel<T, N, RR, MAP_ACC_MS, NT>), grid, dim3(SH::NTH), lds, st, a);
       break;
@@ -48,10 +44,6 @@ void xreg_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
       break;
     case MAP_ACC_EM:
       hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_ACC_EM>), grid, dim3(SH::NTH), lds, st, a);
-      break;
-    case MAP_LANCZOS:   // fp64 only
-      if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_LANCZOS>), grid, dim3(SH::NTH), lds, st, a);
       break;
     default:
       hipLaunchKernelGGL((xpass_p2_kernel<T, N, RR, MAP_ACC_MS>), grid, dim3(SH::NTH), lds, st, a);

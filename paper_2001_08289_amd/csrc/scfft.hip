@@ -17,6 +17,7 @@
 #include <tuple>
 #include <vector>
 
+#include "kernels_lanczos.hpp"
 #include "launch.hpp"
 #include "scfft.h"
 
@@ -186,7 +187,6 @@ struct Plan {
 };
 
 int map_kind(int kind, bool density) {
-  if (kind == K_LANCZOS) return MAP_LANCZOS;
   if (kind == K_ACC_EM) return MAP_ACC_EM;
   if (kind == K_ACC_MS) return MAP_ACC_MS;
   return density ? MAP_LIN_DENS : MAP_LIN;
@@ -485,12 +485,6 @@ void fill_coef(SolveCoef& c, const SolveSpec& sp, bool density, int d, const dou
       c.ga = 1;
       c.gb = -2;
       c.kz_keep = 1;
-      break;
-    case K_LANCZOS:   // pure Gamma_1 projection, start field e0
-      c.ga = 0;
-      c.gb = 1;
-      c.kz_keep = 0;
-      init = 1.0;
       break;
     case K_POWER: {
       for (int ph = 0; ph < 2; ++ph) {
@@ -1417,14 +1411,18 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
   return SCFFT_OK;
 }
 
-// Lanczos process on Gamma_1 chi Gamma_1 from v_0 = Gamma_1 chi e0 (fp64):
-// the unnormalised three-term recurrence w_j = A w_{j-1} - a_{j-1} w_{j-1}
-// - gamma_{j-1} w_{j-2} runs in the iteration kernels (one x pass and one
-// Gamma pass per step); a_j = (w_j, chi w_j)/(w_j, w_j) (= (w_j, A w_j)/(w_j, w_j)
-// since w_j lies in E), b_j = |w_j|/|w_{j-1}|.  No reorthogonalisation: the
-// extreme Gauss nodes converge first, later copies carry negligible weight.
+// Lanczos process on A = Gamma_1 chi Gamma_1 from v_0 = Gamma_1 chi e0 (fp64)
+// with full reorthogonalisation: q_0 = v_0/|v_0|; step j applies A to q_j
+// (one x pass and one Gamma pass, the power-iteration map with weight chi),
+// removes the components along q_0..q_j by classical Gram-Schmidt twice
+// (a_j = the total removed along q_j), and b_{j+1} = |r|, q_{j+1} = r/b_{j+1}.
+// All vectors stay in the passes' stored spectral form (kernels_lanczos.hpp);
+// the basis lives in a buffer of (steps + 1) vectors allocated for the call.
+// The process stops after `steps` values of a, or when
+// b_{j+1} < 1e-12 max(1, |a_j|) (the Krylov space closed).
 scfft_status lanczos_run(const scfft_problem* prob, int steps, int symbol, hipStream_t st,
-                         std::vector<double>& a, std::vector<double>& b, double* norm0) {
+                         std::vector<double>& a, std::vector<double>& b, double* norm0,
+                         double* b_last = nullptr) {
   if (!prob || !prob->phase || prob->density || steps < 1 || steps > 200 || symbol < 0 ||
       symbol > 2 || bad_e0(prob))
     return SCFFT_ERR_INVALID_ARG;
@@ -1432,45 +1430,124 @@ scfft_status lanczos_run(const scfft_problem* prob, int steps, int symbol, hipSt
   if (rc != SCFFT_OK) return rc;
   std::lock_guard<std::mutex> lk(g_mutex);
   Plan* p = nullptr;
-  SolveSpec lz{};
-  lz.kind = K_LANCZOS;
-  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 1, true, symbol, st, &p, 0,
-                real_ok(lz, prob->d, prob->n));
-  if (rc != SCFFT_OK) return rc;
-  rc = ensure_hist(p, steps + 2);
+  SolveSpec pw{};
+  pw.kind = K_POWER;
+  pw.power_phase = 1;
+  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 1, false, symbol, st, &p, 0,
+                real_ok(pw, prob->d, prob->n));
   if (rc != SCFFT_OK) return rc;
   scfft_options o;
   scfft_default_options(&o);
   o.tol = -1.0;
-  o.max_iter = steps;
+  o.max_iter = steps + 1;
   o.stag_window = 0;
   o.div_factor = 0.0;
   SolveCtl c;
   SolveCoef cf;
-  fill_ctl(c, o, K_LANCZOS, prob->d, prob->e0);
-  fill_coef(cf, lz, false, prob->d, prob->e0, (double)p->M);
-  p->mk = MAP_LANCZOS;
+  fill_ctl(c, o, K_POWER, prob->d, prob->e0);
+  fill_coef(cf, pw, false, prob->d, prob->e0, (double)p->M);
+  p->mk = MAP_LIN;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);
   if (rc != SCFFT_OK) return rc;
-  double ms = 0;
-  rc = run_loop({p}, {prob->phase}, {nullptr}, steps, 32, st, &ms);
-  if (rc != SCFFT_OK) return rc;
-  std::vector<double> hs(2 * (size_t)(steps + 1));
-  SCFFT_HIP(hipMemcpyAsync(hs.data(), p->hist_s, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
-  SCFFT_HIP(hipMemcpyAsync(&c, p->ctl, sizeof(c), hipMemcpyDeviceToHost, st));
-  SCFFT_HIP(hipStreamSynchronize(st));
-  // iterate n >= 1 holds (a_{n-1}, |w_{n-1}|^2); a breakdown at n invalidates n
-  const int last = c.status == SCFFT_ERR_DIVERGED ? c.iter - 1 : std::min(c.iter, steps);
+
+  LzArgs z{};
+  z.X = reinterpret_cast<cx<double>*>(p->X);
+  z.vlen = (long long)p->d * p->Mh;
+  z.H = p->H;
+  z.HP = p->HP;
+  z.half = p->real ? 1 : 0;
+  z.packed = p->packed ? 1 : 0;
+  const int nb = (int)std::min<long long>((z.vlen + kLzThreads - 1) / kLzThreads, 1024);
+  const size_t vbytes = sizeof(cx<double>) * (size_t)z.vlen;
+  void* qbuf = nullptr;
+  double* work = nullptr;   // part [201][nb][2], red [201][2], per-step scalars [steps+1][3]
+  const size_t nwork = (size_t)201 * nb * 2 + 201 * 2 + (size_t)(steps + 1) * 3;
+  if (hipMalloc(&qbuf, vbytes * (size_t)(steps + 1)) != hipSuccess) return SCFFT_ERR_OOM;
+  if (hipMalloc(&work, sizeof(double) * nwork) != hipSuccess) {
+    (void)hipFree(qbuf);
+    return SCFFT_ERR_OOM;
+  }
+  z.Q = static_cast<cx<double>*>(qbuf);
+  z.part = work;
+  z.red = work + (size_t)201 * nb * 2;
+  double* scal = z.red + 201 * 2;
+  const double nd = (double)p->M;
+  auto dots_and_update = [&](int nk, double* save) {
+    z.nk = nk;
+    z.save = save;
+    z.save_k = nk - 1;
+    const dim3 g((unsigned)nb, (unsigned)((nk + kLzGroup - 1) / kLzGroup));
+    hipLaunchKernelGGL(lz_dots_kernel, g, dim3(kLzThreads), 0, st, z);
+    hipLaunchKernelGGL(lz_reduce_kernel, dim3(nk), dim3(kLzThreads), 0, st, z, nb);
+    hipLaunchKernelGGL(lz_update_kernel, dim3(nb), dim3(kLzThreads), 0, st, z);
+  };
+  auto norm = [&](double* save) {
+    z.nk = 1;
+    z.save = save;
+    z.save_k = 0;
+    hipLaunchKernelGGL(lz_norm_kernel, dim3(nb), dim3(kLzThreads), 0, st, z);
+    hipLaunchKernelGGL(lz_reduce_kernel, dim3(1), dim3(kLzThreads), 0, st, z, nb);
+  };
+  auto scale_into = [&](int slot) {
+    z.slot = slot;
+    hipLaunchKernelGGL(lz_scale_kernel, dim3(nb), dim3(kLzThreads), 0, st, z);
+  };
   a.clear();
   b.clear();
-  for (int n = 1; n <= last; ++n) {
-    a.push_back(hs[2 * n]);
-    if (n >= 2) b.push_back(std::sqrt(hs[2 * n + 1] / hs[2 * (n - 1) + 1]));
-  }
-  if (a.empty()) return SCFFT_ERR_INVALID_ARG;   // v_0 = 0: e0 sees no inhomogeneity
-  if (norm0) *norm0 = hs[3];
+  do {
+    // v_0 = Gamma_1 chi e0 (the power map applied to the source e0)
+    rc = launch_iteration(p, prob->phase, nullptr, st, true);
+    if (rc != SCFFT_OK) break;
+    norm(scal);
+    double h[3] = {0, 0, 0};
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(h, scal, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      rc = SCFFT_ERR_DEVICE;
+      break;
+    }
+    // Parseval: X holds the x-spectrum of the field times N^d/n0
+    const double n0 = h[0] * (double)p->n[0] / (nd * nd);
+    if (!(n0 > 0.0) || !std::isfinite(n0)) {
+      rc = SCFFT_ERR_INVALID_ARG;   // v_0 = 0: e0 sees no inhomogeneity
+      break;
+    }
+    if (norm0) *norm0 = n0;
+    scale_into(0);
+    for (int j = 0; j < steps; ++j) {
+      rc = launch_iteration(p, prob->phase, nullptr, st, true);   // X = A q_j
+      if (rc != SCFFT_OK) break;
+      double* sj = scal + 3 * (size_t)j;
+      dots_and_update(j + 1, sj);       // classical Gram-Schmidt ...
+      dots_and_update(j + 1, sj + 1);   // ... twice
+      norm(sj + 2);
+      if (hipGetLastError() != hipSuccess ||
+          hipMemcpyAsync(h, sj, 3 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        rc = SCFFT_ERR_DEVICE;
+        break;
+      }
+      const double aj = h[0] + h[1], bj = std::sqrt(std::max(h[2], 0.0));
+      if (!std::isfinite(aj) || !std::isfinite(bj)) {
+        rc = SCFFT_ERR_DEVICE;
+        break;
+      }
+      a.push_back(aj);
+      if (j == steps - 1 || bj < 1e-12 * std::max(1.0, std::fabs(aj))) {
+        if (b_last) *b_last = j == steps - 1 ? bj : 0.0;
+        break;
+      }
+      b.push_back(bj);
+      scale_into(j + 1);
+    }
+  } while (false);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(qbuf);
+  (void)hipFree(work);
+  if (rc != SCFFT_OK) return rc;
+  if (a.empty()) return SCFFT_ERR_INVALID_ARG;
   return SCFFT_OK;
 }
 
@@ -1529,12 +1606,14 @@ scfft_status scfft_lanczos(const scfft_problem* prob, int steps, int symbol, voi
                            double* a, double* b, double* norm0, int* m) {
   if (!a || !b || !m) return SCFFT_ERR_INVALID_ARG;
   std::vector<double> va, vb;
+  double bl = 0.0;
   scfft_status rc = lanczos_run(prob, steps, symbol, reinterpret_cast<hipStream_t>(stream), va, vb,
-                                norm0);
+                                norm0, &bl);
   if (rc != SCFFT_OK) return rc;
   *m = (int)va.size();
   for (size_t i = 0; i < va.size(); ++i) a[i] = va[i];
   for (size_t i = 0; i < vb.size(); ++i) b[i] = vb[i];
+  b[va.size() - 1] = bl;
   return SCFFT_OK;
 }
 
@@ -1544,33 +1623,18 @@ scfft_status scfft_estimate_interval_lanczos(const scfft_problem* prob, int step
                                              double* mu_min, double* mu_max) {
   if (!(rel_weight >= 0.0) || !(rel_weight < 1.0)) return SCFFT_ERR_INVALID_ARG;
   std::vector<double> va, vb, node, w0;
-  double n0 = 0;
   scfft_status rc = lanczos_run(prob, steps, symbol, reinterpret_cast<hipStream_t>(stream), va, vb,
-                                &n0);
+                                nullptr);
   if (rc != SCFFT_OK) return rc;
   gauss_rule(va, vb, node, w0);
-  // Cullum-Willoughby: a simple node that is also an eigenvalue of T without
-  // its first row and column comes from rounding (lost orthogonality), not
-  // from the measure of v_0; numerically multiple nodes are copies and stay
-  std::vector<double> nhat, whatv;
-  if (va.size() >= 2) {
-    std::vector<double> ah(va.begin() + 1, va.end()), bh(vb.begin() + 1, vb.end());
-    gauss_rule(ah, bh, nhat, whatv);
-  }
   double tot = 0;
   for (double w : w0) tot += w;
   double lo = INFINITY, hi = -INFINITY;
-  for (size_t i = 0; i < node.size(); ++i) {
-    int copies = 0;
-    for (double t : node) copies += std::fabs(t - node[i]) < 1e-8 ? 1 : 0;
-    bool spurious = false;
-    if (copies < 2)
-      for (double t : nhat) spurious = spurious || std::fabs(t - node[i]) < 1e-8;
-    if (!spurious && w0[i] > rel_weight * tot) {
+  for (size_t i = 0; i < node.size(); ++i)
+    if (w0[i] > rel_weight * tot) {
       lo = std::min(lo, node[i]);
       hi = std::max(hi, node[i]);
     }
-  }
   if (!(lo > 0.0) || !(hi < 1.0) || !(lo <= hi)) return SCFFT_ERR_INVALID_ARG;
   const double al = 1.0 / hi - 1.0, be = 1.0 / lo - 1.0;
   // floating-point stability of the accelerated scheme: alpha beta = 1

@@ -402,11 +402,12 @@ def lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="rotated", stream=Non
                             b, ctypes.byref(n0), ctypes.byref(m))
     if rc != OK:
         raise ScfftError(rc, "scfft_lanczos")
-    return {"a": np.array(a[:m.value]), "b": np.array(b[:max(0, m.value - 1)]), "norm0": n0.value}
+    return {"a": np.array(a[:m.value]), "b": np.array(b[:max(0, m.value - 1)]),
+            "b_last": b[m.value - 1], "norm0": n0.value}
 
 
 def estimate_interval_lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="rotated",
-                              rel_weight=1e-6, stream=None) -> dict:
+                              rel_weight=1e-20, stream=None) -> dict:
     """scfft_estimate_interval_lanczos: raw and stability-symmetrised interval."""
     prob, keep = make_problem(phase, None, 1.0, e0)
     v = [ctypes.c_double() for _ in range(6)]

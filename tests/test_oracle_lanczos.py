@@ -26,10 +26,41 @@ def test_gauss_rule_matches_dense_spectral_measure(symbol):
     for k in range(0, 2 * len(a)):
         mk = np.sum(w * lam ** k)
         assert abs(np.sum(wts * theta ** k) - mk) < 1e-9 * max(1.0, abs(mk)) * n0
-    keep = w > 1e-6 * w.sum()
+    keep = w > lanczos.REL_WEIGHT * w.sum()
     mu_min, mu_max = lanczos.support_estimate(a, b, n0)
     assert abs(mu_min - lam[keep].min()) < 1e-10
     assert abs(mu_max - lam[keep].max()) < 1e-10
+    # what falls below the cut-off is rounding: the zero-weight eigenspaces
+    assert np.all(w[~keep] < 1e-26 * w.sum())
+
+
+def test_small_weight_extreme_node_is_support():
+    """A random 7 x 9 map (no symmetry: simple eigenvalues).  The applied
+    field e0 = (cos t, sin t) is turned until the top eigenvalue of the dense
+    Gamma_1 chi Gamma_1 carries a weight of about 1e-10 of the total: that
+    eigenvalue still belongs to the support, and the estimate must return it
+    (a cut-off of 1e-6 would drop it)."""
+    chi = inputs.random_phase((7, 9), 0.4, seed=4)
+    d, m = 2, chi.size
+    G = dense.gamma_dense(chi.shape, "rotated")
+    X = np.diag(np.tile(chi.ravel().astype(float), d))
+    lam, phi = np.linalg.eigh(G @ X @ G)
+    ux = phi.conj().T @ (G @ (X @ np.concatenate([np.ones(m), np.zeros(m)])))
+    uy = phi.conj().T @ (G @ (X @ np.concatenate([np.zeros(m), np.ones(m)])))
+    tot = np.abs(ux) ** 2 + np.abs(uy) ** 2
+    top = int(np.flatnonzero(tot > 1e-12 * tot.sum()).max())
+    assert lam[top] < 1 - 1e-6 and abs(lam[top] - lam[top - 1]) > 1e-6
+    t0 = np.arctan2(-ux[top].real, uy[top].real)      # weight of lam[top] vanishes at t0
+    t = t0 + 1e-4
+    e0 = (np.cos(t), np.sin(t))
+    w = np.abs(np.cos(t) * ux + np.sin(t) * uy) ** 2
+    rel = w[top] / w.sum()
+    assert 1e-12 < rel < 1e-8
+    a, b, n0 = lanczos.lanczos(chi, e0, d * m, "rotated")
+    mu_min, mu_max = lanczos.support_estimate(a, b, n0)
+    assert abs(mu_max - lam[top]) < 1e-9
+    # the old 1e-6 cut-off would have returned the next node instead
+    assert lanczos.support_estimate(a, b, n0, rel_weight=1e-6)[1] < lam[top] - 1e-6
 
 
 def test_laminate_measure_is_one_point():

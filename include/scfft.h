@@ -27,7 +27,12 @@
  * Conventions for every entry point:
  *   - grids: axis 0 (x) varies fastest; voxel (x, y, z) is at
  *     x + n[0]*(y + n[1]*z); vector fields are component-major [d][N^d];
- *     every n[i] must factor into 2, 3 and 5 and lie in [2, 4096];
+ *     the periodic cell is the unit square (cube), so a voxel is 1/n[i]
+ *     wide along axis i; every n[i] must factor into 2, 3 and 5 and lie in
+ *     [2, 4096], and the last axis must fit one workgroup's transform of all
+ *     d components: d * n[d-1] <= 8192 in fp32 (3D: n[2] <= 2730) and
+ *     <= 4096 in fp64 (2D: n[1] <= 2048; 3D: n[2] <= 1365); larger grids
+ *     return SCFFT_ERR_INVALID_ARG;
  *   - every pointer documented "device" is a device address on the current
  *     HIP device, owned by the caller, and must stay valid until the call
  *     returns; "host" pointers likewise; the library never frees them;
@@ -65,13 +70,16 @@ typedef enum {
                      scheme scalars stay fp64 */
 } scfft_precision;
 
-/* Discrete reading of Gamma_1 (eq. J11), theta_j = 2 pi m_j / n_j:
- *  ROTATED  n_j = sin(theta_j/2) prod_{l != j} cos(theta_l/2); modes with
- *           n = 0 but m != 0 use n_j = [m_j == n_j/2];
- *  SPECTRAL the literal integer wavevector, m_j in (-n_j/2, n_j/2]; Nyquist
- *           components are zeroed at modes that also have a non-zero
- *           non-Nyquist component;
- *  NETWORK  n_j = exp(i theta_j) - 1, used as n n^H/|n|^2.               */
+/* Discrete reading of Gamma_1 (eq. J11), theta_j = 2 pi m_j / n_j, on the
+ * unit cell (difference quotients carry 1/h_j = n_j):
+ *  ROTATED  n_j = n_j sin(theta_j/2) prod_{l != j} cos(theta_l/2), the
+ *           difference across a voxel averaged over the other axes; modes
+ *           with n = 0 but m != 0 use n_j = n_j [m_j == n_j/2];
+ *  SPECTRAL the literal wavevector (over 2 pi), m_j in (-n_j/2, n_j/2];
+ *           Nyquist components are zeroed at modes that also have a
+ *           non-zero non-Nyquist component;
+ *  NETWORK  n_j = n_j (exp(i theta_j) - 1), the forward difference of the
+ *           resistor network of section 2, used as n n^H/|n|^2.          */
 typedef enum {
   SCFFT_GAMMA_ROTATED = 0,
   SCFFT_GAMMA_SPECTRAL = 1,

@@ -264,6 +264,26 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
 scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_options* opt,
                                     scfft_c64* tensor, int* iterations);
 
+/* Execution choices for a problem and options: the plan scfft_solve uses.
+ * Unless SCFFT_TUNE=0, the first plan of a configuration (grid, precision,
+ * scheme's local map, symbol, field mode) is chosen by the autotuner, which
+ * times every candidate of each pass on the real kernels with the solve's
+ * own coefficients (per layout: kx = 0 / n0/2 packing, padded row pitch,
+ * nontemporal x-pass streams; per pass: register radix and tile width) and
+ * keeps the fastest; the choice is kept for the process, and appended to the
+ * file SCFFT_TUNE_CACHE names (keyed by GPU architecture), which later
+ * processes read.  info (host, cap >= 10 entries) receives: [0] real-field
+ * mode, [1] kx = 0 and n0/2 packed in one column (2D), [2] rows padded to
+ * 128-byte lines, [3] nontemporal x-pass streams, [4] x-pass register radix
+ * (0: LDS-staged mixed radix), [5] Gamma-pass register radix (0: mixed
+ * radix), [6] Gamma-pass tile width, [7] 3D y-pass tile width (0 in 2D),
+ * [8] 1 if the autotuner chose, 0 for the built-in rules, [9] rows per
+ * x-pass workgroup.  Environment overrides (SCFFT_XR, SCFFT_GR,
+ * SCFFT_LINE_C, SCFFT_YC, SCFFT_PACK, SCFFT_PITCH, SCFFT_NT, SCFFT_R16=0)
+ * force single choices over both. */
+scfft_status scfft_plan_info(const scfft_problem* prob, const scfft_options* opt, int* info,
+                             int cap);
+
 /* Average device duration (ms, HIP events on opt->stream) of each kernel of
  * one iteration over `iters` iterations of the given solve configuration:
  * ms[0] real-space x pass, ms[1] Gamma pass (last axis), ms[2] forward y pass

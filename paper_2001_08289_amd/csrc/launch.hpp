@@ -38,20 +38,27 @@ constexpr int line_radix() {
     default: break;               \
   }
 
-// Real-field x pass (power-of-two n0): local map `mk`, own streams
-// nontemporal when `nt`.  grid = (row-pair blocks, d, solves).
+// Real-field x pass (power-of-two n0) with register radix xr (4 or 8):
+// local map `mk`, own streams nontemporal when `nt`.  grid = (row-pair
+// blocks, d, solves).
 template <typename T>
-void launch_xpass_real(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, bool nt);
+void launch_xpass_real(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, bool nt, int xr);
 
-// Complex register-resident x pass (power-of-two n0).
+// Complex register-resident x pass (power-of-two n0), register radix xr.
 template <typename T>
-void launch_xpass_reg(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk);
+void launch_xpass_reg(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, int xr);
 
 // Register-resident strided pass over lines of length n: D = 2 / 3 the Gamma
 // pass of a 2D / 3D grid (all components), D = 1 a plain 3D y pass; a.C is
-// the tile width (one of 1, 2, 4, 8; anything else the widest that fits).
+// the tile width (one of 1, 2, 4, 8; anything else the widest that fits);
+// gr the register radix (D = 2: 4 or 8; D = 1, 3: 8).
 template <typename T, int D>
-void launch_line_reg(const GArgs& a, dim3 grid, hipStream_t st, int n);
+void launch_line_reg(const GArgs& a, dim3 grid, hipStream_t st, int n, int gr);
+
+// Rows per workgroup of the register x pass and the widest strided tile,
+// for a line length, precision (sizeof T), component count and radix.
+int xpass_lines(int n, int esz, int xr);
+int line_tile_max(int n, int esz, int D, int gr);
 
 // fp64 Gamma pass of 2048-point columns with radix-16 register FFTs.
 void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);

@@ -36,6 +36,42 @@ void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st) {
   hipLaunchKernelGGL((line_p2_kernel<double, 2048, 16, 2, 0>), grid, dim3(SH::NTH), lds, st, a);
 }
 
+int xpass_lines(int n, int esz, int xr) {
+  int r = 1;
+  if (xr == 8) {
+#define C_(N) r = XPassShape<N, 8>::LINES
+    SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  } else {
+#define C_(N) r = XPassShape<N, 4>::LINES
+    SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  }
+  (void)esz;
+  return r;
+}
+
+namespace {
+template <typename T, int D, int RR>
+int tile_max_t(int n) {
+  int r = 1;
+#define C_(N) r = (N >= RR) ? LineShape<T, N, (N >= RR ? RR : N), D>::C : 1
+  SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  return r;
+}
+template <typename T>
+int tile_max_r(int n, int D, int gr) {
+  if (gr == 16) return D == 2 ? tile_max_t<T, 2, 16>(n) : 1;
+  if (gr == 4) return D == 1 ? tile_max_t<T, 1, 4>(n) : D == 2 ? tile_max_t<T, 2, 4>(n) : tile_max_t<T, 3, 4>(n);
+  return D == 1 ? tile_max_t<T, 1, 8>(n) : D == 2 ? tile_max_t<T, 2, 8>(n) : tile_max_t<T, 3, 8>(n);
+}
+}  // namespace
+
+int line_tile_max(int n, int esz, int D, int gr) {
+  return esz == 8 ? tile_max_r<float>(n, D, gr) : tile_max_r<double>(n, D, gr);
+}
+
 template void launch_xpass_generic<float>(const XArgs&, dim3, size_t, hipStream_t);
 template void launch_xpass_generic<double>(const XArgs&, dim3, size_t, hipStream_t);
 template void launch_line_generic<float>(const GArgs&, dim3, size_t, hipStream_t);

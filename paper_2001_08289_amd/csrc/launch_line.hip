@@ -10,7 +10,7 @@
 namespace scfft {
 namespace {
 
-template <typename T, int N, int D, int CW, int RR = line_radix<T, N, D>()>
+template <typename T, int N, int D, int CW, int RR>
 void line_cw(const GArgs& a, dim3 grid, hipStream_t st) {
   using SH = LineShape<T, N, RR, D, CW>;
   const size_t lds = (size_t)SH::LDS;
@@ -26,17 +26,17 @@ void line_cw(const GArgs& a, dim3 grid, hipStream_t st) {
   hipLaunchKernelGGL((line_p2_kernel<T, N, RR, D, CW>), grid, dim3(SH::NTH), lds, st, a);
 }
 
-template <typename T, int N, int D>
+template <typename T, int N, int D, int RR>
 void line_n(const GArgs& a, dim3 grid, hipStream_t st) {
-  if constexpr (D == 3 && N > 1024) {
+  if constexpr ((D == 3 && N > 1024) || N < RR) {
     return;   // 3D Gamma lines are at most 1024 points (host limit)
   } else {
     switch (a.C) {
-      case 1: line_cw<T, N, D, 1>(a, grid, st); break;
-      case 2: line_cw<T, N, D, 2>(a, grid, st); break;
-      case 4: line_cw<T, N, D, 4>(a, grid, st); break;
-      case 8: line_cw<T, N, D, 8>(a, grid, st); break;
-      default: line_cw<T, N, D, 0>(a, grid, st); break;
+      case 1: line_cw<T, N, D, 1, RR>(a, grid, st); break;
+      case 2: line_cw<T, N, D, 2, RR>(a, grid, st); break;
+      case 4: line_cw<T, N, D, 4, RR>(a, grid, st); break;
+      case 8: line_cw<T, N, D, 8, RR>(a, grid, st); break;
+      default: line_cw<T, N, D, 0, RR>(a, grid, st); break;
     }
   }
 }
@@ -44,10 +44,17 @@ void line_n(const GArgs& a, dim3 grid, hipStream_t st) {
 }  // namespace
 
 template <>
-void launch_line_reg<SCFFT_T, SCFFT_D>(const GArgs& a, dim3 grid, hipStream_t st, int n) {
-#define C_(N) line_n<SCFFT_T, N, SCFFT_D>(a, grid, st)
-  SCFFT_P2_SWITCH(n, C_)
+void launch_line_reg<SCFFT_T, SCFFT_D>(const GArgs& a, dim3 grid, hipStream_t st, int n, int gr) {
+  // the 2D Gamma pass offers radix 4 and 8; the 3D passes radix 8
+  if (SCFFT_D == 2 && gr == 4) {
+#define C_(N) line_n<SCFFT_T, N, SCFFT_D, 4>(a, grid, st)
+    SCFFT_P2_SWITCH(n, C_)
 #undef C_
+  } else {
+#define C_(N) line_n<SCFFT_T, N, SCFFT_D, 8>(a, grid, st)
+    SCFFT_P2_SWITCH(n, C_)
+#undef C_
+  }
 }
 
 }  // namespace scfft

@@ -9,7 +9,7 @@
 namespace scfft {
 namespace {
 
-template <typename T, int N, bool NT, int RR = xpass_radix<T, N>()>
+template <typename T, int N, bool NT, int RR>
 void xreal_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   using SH = XPassShape<N, RR>;
   const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
@@ -30,7 +30,7 @@ void xreal_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   }
 }
 
-template <typename T, int N, int RR = xpass_radix<T, N>()>
+template <typename T, int N, int RR>
 void xreg_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
   using SH = XPassShape<N, RR>;
   const size_t lds = std::max((size_t)SH::LINES * P2Plan<N, RR>::LP * sizeof(cx<T>),
@@ -54,23 +54,42 @@ void xreg_t(const XArgs& a, dim3 grid, hipStream_t st, int mk) {
 }  // namespace
 
 template <>
-void launch_xpass_real<SCFFT_T>(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, bool nt) {
+void launch_xpass_real<SCFFT_T>(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, bool nt,
+                                int xr) {
   if (nt) {
-#define C_(N) xreal_t<SCFFT_T, N, true>(a, grid, st, mk)
-    SCFFT_P2_SWITCH(n0, C_)
+    if (xr == 8) {
+#define C_(N) xreal_t<SCFFT_T, N, true, 8>(a, grid, st, mk)
+      SCFFT_P2_SWITCH(n0, C_)
 #undef C_
+    } else {
+#define C_(N) xreal_t<SCFFT_T, N, true, 4>(a, grid, st, mk)
+      SCFFT_P2_SWITCH(n0, C_)
+#undef C_
+    }
   } else {
-#define C_(N) xreal_t<SCFFT_T, N, false>(a, grid, st, mk)
-    SCFFT_P2_SWITCH(n0, C_)
+    if (xr == 8) {
+#define C_(N) xreal_t<SCFFT_T, N, false, 8>(a, grid, st, mk)
+      SCFFT_P2_SWITCH(n0, C_)
 #undef C_
+    } else {
+#define C_(N) xreal_t<SCFFT_T, N, false, 4>(a, grid, st, mk)
+      SCFFT_P2_SWITCH(n0, C_)
+#undef C_
+    }
   }
 }
 
 template <>
-void launch_xpass_reg<SCFFT_T>(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk) {
-#define C_(N) xreg_t<SCFFT_T, N>(a, grid, st, mk)
-  SCFFT_P2_SWITCH(n0, C_)
+void launch_xpass_reg<SCFFT_T>(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk, int xr) {
+  if (xr == 8) {
+#define C_(N) xreg_t<SCFFT_T, N, 8>(a, grid, st, mk)
+    SCFFT_P2_SWITCH(n0, C_)
 #undef C_
+  } else {
+#define C_(N) xreg_t<SCFFT_T, N, 4>(a, grid, st, mk)
+    SCFFT_P2_SWITCH(n0, C_)
+#undef C_
+  }
 }
 
 }  // namespace scfft

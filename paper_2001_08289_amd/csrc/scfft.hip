@@ -14,6 +14,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -90,68 +91,40 @@ bool pack_pays(int n0, int c, int nsolve, int dev) {
   return (tu + cus - 1) / cus > (tp + cus - 1) / cus;
 }
 
-template <typename T, int N>
-int xlines_p2() { return XPassShape<N, xpass_radix<T, N>()>::LINES; }
-template <typename T, int N, int D>
-int linec_p2() { return LineShape<T, N, line_radix<T, N, D>(), D>::C; }
-
-// Tile width of the strided passes: the widest that fits, or a narrower one
-// from SCFFT_LINE_C (a power of two) for tuning.
-int tuned_c(int cmax) {
-  const char* e = std::getenv("SCFFT_LINE_C");
-  if (!e) return cmax;
-  const int v = std::atoi(e);
-  if (v == 1 || v == 2 || v == 4 || v == 8) return std::min(v, cmax);
-  return cmax;
-}
-
-
-// Radix 16 (2048 = 16*8*16, one LDS exchange fewer) measured faster only for
-// the fp64 Gamma pass of 2048^2 grids (115 -> 104 us), where it is the
-// default (SCFFT_R16=0 turns it off); everywhere else radix 8 or 4 keeps more
-// waves resident.
-int r16_linec_f64_2048() { return LineShape<double, 2048, 16, 2>::C; }
-
-int p2_xlines(int n, int prec) {
-  int r = 1;
-#define C_(N) r = prec == SCFFT_FP32 ? xlines_p2<float, N>() : xlines_p2<double, N>()
-  SCFFT_P2_SWITCH(n, C_)
-#undef C_
-  return r;
-}
-
-int p2_linec(int n, int prec, int D) {
-  int r = 1;
-  if (prec == SCFFT_FP32) {
-    if (D == 1) {
-#define C_(N) r = linec_p2<float, N, 1>()
-      SCFFT_P2_SWITCH(n, C_)
-#undef C_
-    } else if (D == 2) {
-#define C_(N) r = linec_p2<float, N, 2>()
-      SCFFT_P2_SWITCH(n, C_)
-#undef C_
-    } else {
-#define C_(N) r = linec_p2<float, N, 3>()
-      SCFFT_P2_SWITCH(n, C_)
-#undef C_
-    }
-  } else {
-    if (D == 1) {
-#define C_(N) r = linec_p2<double, N, 1>()
-      SCFFT_P2_SWITCH(n, C_)
-#undef C_
-    } else if (D == 2) {
-#define C_(N) r = linec_p2<double, N, 2>()
-      SCFFT_P2_SWITCH(n, C_)
-#undef C_
-    } else {
-#define C_(N) r = linec_p2<double, N, 3>()
-      SCFFT_P2_SWITCH(n, C_)
-#undef C_
-    }
+// ------------------------------------------------------------ plan knobs
+// Speed choices of a plan.  Every value gives the same iterates up to
+// rounding (each is parity-tested); 0 / -1 means "the measured rule" below.
+struct Knobs {
+  int xr = 0;      // x pass register radix: 4 or 8
+  int gr = 0;      // Gamma pass register radix: 2D 4 or 8 (fp64 2048-point lines also 16); 3D 8
+  int gC = 0;      // Gamma pass tile width: 1, 2, 4, 8 (capped by the LDS budget)
+  int yC = 0;      // 3D y pass tile width: 1, 2, 4, 8
+  int pack = -1;   // 2D real mode: kx = 0 and n0/2 share column 0
+  int nt = -1;     // real mode: the x pass streams its own arrays nontemporally
+  int pitch = -1;  // real mode: rows of X padded to 128-byte lines
+  bool operator==(const Knobs& o) const {
+    return xr == o.xr && gr == o.gr && gC == o.gC && yC == o.yC && pack == o.pack && nt == o.nt &&
+           pitch == o.pitch;
   }
-  return r;
+};
+
+// Environment overrides force a knob (tests force each candidate this way).
+int env_int(const char* name, int dflt) {
+  const char* e = std::getenv(name);
+  return e ? std::atoi(e) : dflt;
+}
+
+// Register radix rules (measured on MI355X, fp32 and fp64): radix 4 (twice
+// the threads per line, more waves in flight) for the x pass up to n0 = 1024
+// (fp64: 2048) and for the 2D Gamma pass up to 1024; radix 8 (fewer LDS
+// exchanges) for longer lines and the 3D strided passes; radix 16 (one
+// exchange fewer again) for the fp64 Gamma pass of 2048-point lines
+// (115 -> 104 us).
+int rule_xr(int n, int esz) { return (n <= 1024 || (esz == 16 && n <= 2048)) ? 4 : 8; }
+int rule_gr(int n, int esz, int d) {
+  if (d != 2) return 8;
+  if (esz == 16 && n == 2048 && env_int("SCFFT_R16", 1) != 0) return 16;
+  return n <= 1024 ? 4 : 8;
 }
 
 struct Plan {
@@ -177,7 +150,8 @@ struct Plan {
   int xlines = 0, xL = 1, xblocks = 0;
   int gC = 1, yC = 1;
   bool p2x = false, p2g = false, p2y = false;   // register-resident passes
-  bool r16x = false, r16g = false, r16y = false; // radix-16 variants (fp64 2048 Gamma pass)
+  Knobs kn;                                      // resolved speed choices
+  bool tuned = false;                            // kn came from the autotuner
   int mk = MAP_LIN;                              // local map of the current solves
   bool real = false;                             // real-field mode (half spectra)
   bool packed = false;                           // 2D real mode: kx = 0 and n0/2 share column 0
@@ -237,9 +211,11 @@ scfft_status ensure_hist(Plan* p, int cap) {
 }
 
 // Every execution-path choice and buffer size of a plan (host only, no
-// device work besides reading the compute-unit count).
+// device work besides reading the compute-unit count).  `want` holds the
+// tuner's choices (unset fields follow the rules); environment overrides
+// win over both.
 void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, bool st, int symbol,
-                bool real) {
+                bool real, const Knobs& want = Knobs()) {
   const int n2 = d == 3 ? n[2] : 1;
   p->dev = dev;
   p->d = d;
@@ -253,6 +229,7 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   p->M = (long long)n[0] * n[1] * n2;
   p->esz = prec == SCFFT_FP32 ? 8 : 16;
   p->real = real;
+  const int esz = (int)p->esz;
   const int el = elems_for(prec);
   const int nlast = n[d - 1];
   p->xlines = (int)(p->M / n[0]);
@@ -260,38 +237,72 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   p->p2g = is_p2(nlast) && !std::getenv("SCFFT_NO_P2") && (d == 2 || nlast <= 1024);
   p->H = real ? n[0] / 2 + 1 : n[0];
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
-  p->r16x = false;
-  {
-    const char* e = std::getenv("SCFFT_R16");
-    p->r16g = d == 2 && nlast == 2048 && prec == SCFFT_FP64 && p->p2g && !(e && std::atoi(e) == 0);
-  }
-  p->r16y = false;
+  Knobs& k = p->kn;
+  k = Knobs();
+  // x pass radix
   if (p->p2x) {
-    p->xL = p2_xlines(n[0], prec);
+    k.xr = env_int("SCFFT_XR", want.xr ? want.xr : rule_xr(n[0], esz));
+    if (k.xr != 4 && k.xr != 8) k.xr = rule_xr(n[0], esz);
+    if (n[0] < k.xr) k.xr = 4;
+    p->xL = xpass_lines(n[0], esz, k.xr);
   } else {
+    k.xr = 0;
     p->xL = std::max(1, std::min(el / n[0], p->xlines));
   }
   p->xblocks = real ? (p->xlines / 2 + p->xL - 1) / p->xL : (p->xlines + p->xL - 1) / p->xL;
-  p->gC = p->r16g ? r16_linec_f64_2048()
-        : p->p2g ? tuned_c(p2_linec(nlast, prec, d))
-                 : std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
-  p->yC = d == 3 ? (p->p2y ? tuned_c(p2_linec(n[1], prec, 1))
-                           : std::min(pow2_floor(std::max(1, el / n[1])), n[0]))
-                 : 1;
-  // the packed column is unpacked by the register Gamma pass (2D)
-  p->packed = real && d == 2 && p->p2g &&
-              (p->r16g || pack_pays(n[0], p->gC, nsolve, dev));
+  // Gamma pass radix and tile width
+  if (p->p2g) {
+    k.gr = env_int("SCFFT_GR", want.gr ? want.gr : rule_gr(nlast, esz, d));
+    const bool r16ok = d == 2 && nlast == 2048 && esz == 16;
+    if (d != 2) k.gr = 8;
+    if (k.gr == 16 && !r16ok) k.gr = rule_gr(nlast, esz, d) == 16 ? 8 : rule_gr(nlast, esz, d);
+    if (k.gr != 4 && k.gr != 8 && k.gr != 16) k.gr = rule_gr(nlast, esz, d);
+    if (env_int("SCFFT_R16", 1) == 0 && k.gr == 16) k.gr = 8;
+    const int cmax = k.gr == 16 ? line_tile_max(nlast, esz, 2, 16) : line_tile_max(nlast, esz, d, k.gr);
+    const int c = env_int("SCFFT_LINE_C", want.gC ? want.gC : cmax);
+    k.gC = (c == 1 || c == 2 || c == 4 || c == 8) ? std::min(c, cmax) : cmax;
+    if (k.gr == 16) k.gC = cmax;   // one instantiation: the widest tile
+  } else {
+    k.gr = 0;
+    const int cmax = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
+    const int c = env_int("SCFFT_LINE_C", want.gC ? want.gC : cmax);
+    k.gC = c >= 1 ? std::min(pow2_floor(c), cmax) : cmax;
+  }
+  p->gC = k.gC;
+  // 3D y pass tile width
+  if (d == 3 && p->p2y) {
+    const int cmax = line_tile_max(n[1], esz, 1, 8);
+    const int c = env_int("SCFFT_YC", env_int("SCFFT_LINE_C", want.yC ? want.yC : cmax));
+    k.yC = (c == 1 || c == 2 || c == 4 || c == 8) ? std::min(c, cmax) : cmax;
+  } else if (d == 3) {
+    const int cmax = std::min(pow2_floor(std::max(1, el / n[1])), n[0]);
+    const int c = env_int("SCFFT_YC", env_int("SCFFT_LINE_C", want.yC ? want.yC : cmax));
+    k.yC = c >= 1 ? std::min(pow2_floor(c), cmax) : cmax;
+  } else {
+    k.yC = 1;
+  }
+  p->yC = k.yC;
+  // 2D real mode: pack kx = 0 and kx = n0/2 into one column (the register
+  // Gamma pass unpacks it); the rule packs when that lowers the number of
+  // Gamma-pass workgroups the busiest CU runs, and for the radix-16 pass
+  if (real && d == 2 && p->p2g) {
+    const int dflt = want.pack >= 0 ? want.pack
+                   : (k.gr == 16 || pack_pays(n[0], p->gC, nsolve, dev)) ? 1 : 0;
+    k.pack = env_int("SCFFT_PACK", dflt) != 0 ? 1 : 0;
+  } else {
+    k.pack = 0;
+  }
+  p->packed = k.pack != 0;
   if (p->packed) p->H = n[0] / 2;
-  // 3D real mode: rows of X start on 128-byte cache lines, so that a strided
+  // real mode: rows of X start on 128-byte cache lines, so that a strided
   // pass's tile of adjacent columns shares lines only with its neighbours in
-  // the same row (256^3: z pass with Gamma 178 -> 148 us in fp32, 560 -> 440
-  // us in fp64; in 2D neutral or slightly slower, so not there;
-  // SCFFT_PITCH=0/1 forces either)
+  // the same row (rule: 3D, where 256^3 gained 178 -> 148 us in the fp32 z
+  // pass and 560 -> 440 us in fp64; neutral or slightly slower in 2D)
   {
-    const int per_line = 128 / (int)p->esz;
-    const char* e = std::getenv("SCFFT_PITCH");
-    const bool pad = real && (e ? std::atoi(e) != 0 : d == 3);
-    p->HP = pad ? (p->H + per_line - 1) / per_line * per_line : p->H;
+    const int per_line = 128 / esz;
+    k.pitch = real ? (env_int("SCFFT_PITCH", want.pitch >= 0 ? want.pitch : (d == 3 ? 1 : 0)) != 0)
+                   : 0;
+    p->HP = k.pitch ? (p->H + per_line - 1) / per_line * per_line : p->H;
   }
   p->Mh = (long long)p->HP * n[1] * n2;
   const size_t field = (size_t)nsolve * d * p->M * p->esz;
@@ -299,14 +310,15 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   const size_t xfield = real ? (size_t)nsolve * d * p->Mh * p->esz : field;
   const size_t rfield = real ? field / 2 : field;
   // real mode: the x pass streams the phase map, E_prev and the H'' slots
-  // nontemporally when the half spectrum and E_prev alone exceed the 256 MB
-  // Infinity Cache (measured: 256^3 fp32 and fp64 gain; 2048^2 fp32 and fp64
-  // lose, the slots being touched only at phase-1 voxels; SCFFT_NT=0/1
-  // forces either)
+  // nontemporally (rule: when the half spectrum and E_prev alone exceed the
+  // 256 MB Infinity Cache; measured: 256^3 fp32 and fp64 gain, 2048^2 fp32 and
+  // fp64 lose, the slots being touched only at phase-1 voxels)
   {
     const size_t foot = xfield + rfield;
-    const char* e = std::getenv("SCFFT_NT");
-    p->nt = real && (e ? std::atoi(e) != 0 : foot > kInfinityCacheBytes);
+    k.nt = real ? (env_int("SCFFT_NT", want.nt >= 0 ? want.nt : (foot > kInfinityCacheBytes))
+                   != 0)
+                : 0;
+    p->nt = k.nt != 0;
   }
   p->xbytes = xfield;
   p->rbytes = rfield;
@@ -331,9 +343,283 @@ scfft_status plan_tables(Plan* p, hipStream_t stream) {
   return SCFFT_OK;
 }
 
-// `slot` separates workspaces of same-shaped problems solved together.
+// Allocates the buffers of a shaped plan and fills its tables; the partial
+// sums are sized for at least part_blocks x-pass workgroups per component.
+scfft_status plan_alloc(Plan* p, hipStream_t stream, int part_blocks = 0) {
+  const int d = p->d, nsolve = p->nsolve;
+  auto fail = [&](hipError_t e) {
+    return e == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&p->X, p->xbytes)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&p->Ep, p->rbytes)) != hipSuccess) return fail(e);
+  if (p->st) {
+    if ((e = hipMalloc(&p->S, p->rbytes)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&p->T, p->rbytes)) != hipSuccess) return fail(e);
+  }
+  const size_t pb = (size_t)std::max(part_blocks, p->xblocks);
+  if ((e = hipMalloc(&p->part, sizeof(double) * 5 * (size_t)nsolve * d * pb)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMalloc(&p->ctl, sizeof(SolveCtl) * nsolve)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc(&p->coef, sizeof(SolveCoef) * nsolve)) != hipSuccess) return fail(e);
+  for (int a = 0; a < d; ++a) {
+    if ((e = hipMalloc(&p->tw[a], p->esz * p->n[a])) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&p->sym[a], 2 * sizeof(double) * p->n[a])) != hipSuccess) return fail(e);
+  }
+  scfft_status rc = plan_tables(p, stream);
+  if (rc != SCFFT_OK) return rc;
+  return ensure_hist(p, 64);
+}
+
+// ---------------------------------------------------------------- autotuner
+// One solve's configuration, used to time candidate knobs on the real kernels.
+struct TuneCtx {
+  int mk;
+  const SolveCtl* ctl;
+  const SolveCoef* coef;
+  const uint8_t* phase;
+  const double* density;
+};
+
+using TuneKey = std::tuple<int, int, int, int, int, int, bool, int, bool, int>;
+std::map<TuneKey, Knobs> g_tuned;
+bool g_tune_file_read = false;
+
+bool tuning_enabled() { return env_int("SCFFT_TUNE", 1) != 0; }
+
+std::string arch_name(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+// On-disk cache (SCFFT_TUNE_CACHE): one line per tuned configuration,
+// "arch d n0 n1 n2 prec st symbol real mk xr gr gC yC pack nt pitch".
+void tune_file_read(int dev) {
+  if (g_tune_file_read) return;
+  g_tune_file_read = true;
+  const char* path = std::getenv("SCFFT_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string arch = arch_name(dev);
+  char a[64];
+  int v[16];
+  while (std::fscanf(f, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d", a, &v[0], &v[1],
+                     &v[2], &v[3], &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &v[10], &v[11],
+                     &v[12], &v[13], &v[14], &v[15]) == 17) {
+    if (arch != a) continue;
+    Knobs k;
+    k.xr = v[9];
+    k.gr = v[10];
+    k.gC = v[11];
+    k.yC = v[12];
+    k.pack = v[13];
+    k.nt = v[14];
+    k.pitch = v[15];
+    g_tuned[TuneKey{dev, v[0], v[1], v[2], v[3], v[4], v[5] != 0, v[6], v[7] != 0, v[8]}] = k;
+  }
+  std::fclose(f);
+}
+
+void tune_file_append(const TuneKey& t, const Knobs& k) {
+  const char* path = std::getenv("SCFFT_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d\n",
+               arch_name(std::get<0>(t)).c_str(), std::get<1>(t), std::get<2>(t), std::get<3>(t),
+               std::get<4>(t), std::get<5>(t), (int)std::get<6>(t), std::get<7>(t),
+               (int)std::get<8>(t), std::get<9>(t), k.xr, k.gr, k.gC, k.yC, k.pack, k.nt, k.pitch);
+  std::fclose(f);
+}
+
+scfft_status launch_iteration(Plan* p, const uint8_t* phase, const double* density, hipStream_t st,
+                              bool ignore_done, hipEvent_t* ev);
+scfft_status launch_init(Plan* p, hipStream_t st);
+
+// Sets the per-pass knobs of a shaped plan in place (same buffer layout).
+void set_pass_knobs(Plan* p, int xr, int gr, int gC, int yC) {
+  const int esz = (int)p->esz;
+  if (p->p2x && xr) {
+    p->kn.xr = xr;
+    p->xL = xpass_lines(p->n[0], esz, xr);
+    p->xblocks = p->real ? (p->xlines / 2 + p->xL - 1) / p->xL : (p->xlines + p->xL - 1) / p->xL;
+  }
+  if (gr) p->kn.gr = gr;
+  if (gC) p->kn.gC = p->gC = gC;
+  if (yC) p->kn.yC = p->yC = yC;
+}
+
+// Times every candidate of each pass on scratch plans of every layout
+// (pack / pitch / nontemporal streams) with the solve's own coefficients:
+// per candidate one untimed and three timed iterations, the fastest of the
+// three per pass.  Within a layout the passes are independent, so the i-th
+// candidates of all passes run together; a layout costs the sum of its
+// fastest passes (the y pass twice in 3D); the cheapest layout wins.
+scfft_status autotune(int dev, int d, const int* n, int prec, bool st, int symbol, bool real,
+                      const TuneCtx& tc, hipStream_t stream, Knobs* out) {
+  Plan probe;
+  plan_shape(&probe, dev, d, n, prec, 1, st, symbol, real);
+  const int esz = (int)probe.esz;
+  const int nlast = n[d - 1];
+  std::vector<int> xrs = probe.p2x ? std::vector<int>{4, 8} : std::vector<int>{0};
+  std::vector<std::pair<int, int>> gcs;   // (radix, tile width)
+  if (probe.p2g) {
+    std::vector<int> radices = d == 2 ? std::vector<int>{4, 8} : std::vector<int>{8};
+    if (d == 2 && nlast == 2048 && esz == 16) radices.push_back(16);
+    for (int r : radices) {
+      if (nlast < r) continue;
+      const int cmax = line_tile_max(nlast, esz, d, r);
+      if (r == 16) {
+        gcs.push_back({r, cmax});
+        continue;
+      }
+      for (int c = 1; c <= std::min(cmax, 8); c *= 2) gcs.push_back({r, c});
+    }
+  } else {
+    const int el = elems_for(prec);
+    const int cmax = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
+    for (int c = 1; c <= std::min(cmax, 8); c *= 2) gcs.push_back({0, c});
+  }
+  std::vector<int> ycs{0};
+  if (d == 3) {
+    ycs.clear();
+    const int el = elems_for(prec);
+    const int cmax = probe.p2y ? line_tile_max(n[1], esz, 1, 8)
+                               : std::min(pow2_floor(std::max(1, el / n[1])), n[0]);
+    for (int c = 1; c <= std::min(cmax, 8); c *= 2) ycs.push_back(c);
+  }
+  const std::vector<int> packs = (real && d == 2 && probe.p2g) ? std::vector<int>{0, 1}
+                                                              : std::vector<int>{0};
+  const std::vector<int> bins = real ? std::vector<int>{0, 1} : std::vector<int>{0};
+  int part_blocks = 0;
+  for (int xr : xrs) {
+    Plan t = probe;
+    set_pass_knobs(&t, xr, 0, 0, 0);
+    part_blocks = std::max(part_blocks, t.xblocks);
+  }
+  hipEvent_t ev[10];
+  for (auto& e : ev) SCFFT_HIP(hipEventCreate(&e));
+  double best_cost = INFINITY;
+  Knobs best = probe.kn;
+  scfft_status rc = SCFFT_OK;
+  const size_t rounds = std::max({xrs.size(), gcs.size(), ycs.size()});
+  for (int pack : packs)
+    for (int pitch : bins)
+      for (int nt : bins) {
+        if (rc != SCFFT_OK) break;
+        Knobs lay;
+        lay.pack = pack;
+        lay.pitch = pitch;
+        lay.nt = nt;
+        lay.xr = xrs[0];
+        lay.gr = gcs[0].first;
+        lay.gC = gcs[0].second;
+        lay.yC = ycs[0];
+        Plan* p = new Plan();
+        plan_shape(p, dev, d, n, prec, 1, st, symbol, real, lay);
+        if (p->kn.pack != pack || p->kn.pitch != pitch || p->kn.nt != nt) {
+          free_plan(p);   // the environment forces this layout knob: nothing to time
+          continue;
+        }
+        rc = plan_alloc(p, stream, part_blocks);
+        if (rc == SCFFT_OK) {
+          p->mk = tc.mk;
+          if (hipMemcpyAsync(p->ctl, tc.ctl, sizeof(SolveCtl), hipMemcpyHostToDevice, stream) !=
+                  hipSuccess ||
+              hipMemcpyAsync(p->coef, tc.coef, sizeof(SolveCoef), hipMemcpyHostToDevice,
+                             stream) != hipSuccess)
+            rc = SCFFT_ERR_DEVICE;
+        }
+        if (rc == SCFFT_OK) rc = launch_init(p, stream);
+        std::vector<double> tx(xrs.size(), INFINITY), tg(gcs.size(), INFINITY),
+            ty(ycs.size(), INFINITY);
+        for (size_t i = 0; i < rounds && rc == SCFFT_OK; ++i) {
+          const size_t ix = i % xrs.size(), ig = i % gcs.size(), iy = i % ycs.size();
+          set_pass_knobs(p, xrs[ix], gcs[ig].first, gcs[ig].second, ycs[iy]);
+          for (int rep = 0; rep < 4 && rc == SCFFT_OK; ++rep) {
+            rc = launch_iteration(p, tc.phase, tc.density, stream, true, ev);
+            if (rc != SCFFT_OK) break;
+            if (hipEventSynchronize(ev[d == 3 ? 9 : 7]) != hipSuccess) {
+              rc = SCFFT_ERR_DEVICE;
+              break;
+            }
+            if (rep == 0) continue;
+            float a = 0, b = 0, c = 0, e2 = 0;
+            (void)hipEventElapsedTime(&a, ev[0], ev[1]);
+            (void)hipEventElapsedTime(&b, ev[6], ev[7]);
+            if (d == 3) {
+              (void)hipEventElapsedTime(&c, ev[4], ev[5]);
+              (void)hipEventElapsedTime(&e2, ev[8], ev[9]);
+            }
+            tx[ix] = std::min(tx[ix], (double)a);
+            tg[ig] = std::min(tg[ig], (double)b);
+            ty[iy] = std::min(ty[iy], (double)(c + e2));
+          }
+        }
+        if (rc == SCFFT_OK) {
+          const size_t bx = std::min_element(tx.begin(), tx.end()) - tx.begin();
+          const size_t bg = std::min_element(tg.begin(), tg.end()) - tg.begin();
+          const size_t by = std::min_element(ty.begin(), ty.end()) - ty.begin();
+          const double cost = tx[bx] + tg[bg] + (d == 3 ? ty[by] : 0.0);
+          if (cost < best_cost) {
+            best_cost = cost;
+            best = lay;
+            best.xr = xrs[bx];
+            best.gr = gcs[bg].first;
+            best.gC = gcs[bg].second;
+            best.yC = ycs[by];
+          }
+        }
+        (void)hipStreamSynchronize(stream);
+        free_plan(p);
+      }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc != SCFFT_OK) return rc;
+  *out = best;
+  return SCFFT_OK;
+}
+
+// Knobs for a configuration: the cached tuning (tuned on first use when a
+// solve's configuration is given and tuning is on), else the rules.
+scfft_status knobs_for(int dev, int d, const int* n, int prec, bool st, int symbol, bool real,
+                       const TuneCtx* tc, hipStream_t stream, Knobs* out, bool* tuned) {
+  *out = Knobs();
+  *tuned = false;
+  if (!tuning_enabled() || !tc) return SCFFT_OK;
+  tune_file_read(dev);
+  const int n2 = d == 3 ? n[2] : 1;
+  const TuneKey key{dev, d, n[0], n[1], n2, prec, st, symbol, real, tc->mk};
+  auto it = g_tuned.find(key);
+  if (it == g_tuned.end()) {
+    Knobs k;
+    scfft_status rc = autotune(dev, d, n, prec, st, symbol, real, *tc, stream, &k);
+    if (rc != SCFFT_OK) return rc;
+    it = g_tuned.emplace(key, k).first;
+    tune_file_append(key, k);
+  }
+  *out = it->second;
+  *tuned = true;
+  return SCFFT_OK;
+}
+
+// Knobs already tuned for a configuration (no tuning: for callers that may
+// not allocate), else the rules.
+Knobs cached_knobs(int dev, int d, const int* n, int prec, bool st, int symbol, bool real, int mk,
+                   bool* tuned) {
+  const int n2 = d == 3 ? n[2] : 1;
+  auto it = g_tuned.find(TuneKey{dev, d, n[0], n[1], n2, prec, st, symbol, real, mk});
+  *tuned = tuning_enabled() && it != g_tuned.end();
+  return *tuned ? it->second : Knobs();
+}
+
+// `slot` separates workspaces of same-shaped problems solved together; tc
+// (optional) is one solve's configuration for the autotuner.
 scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int symbol,
-                      hipStream_t stream, Plan** out, int slot = 0, bool real = false) {
+                      hipStream_t stream, Plan** out, int slot = 0, bool real = false,
+                      const TuneCtx* tc = nullptr) {
   int dev = 0;
   SCFFT_HIP(hipGetDevice(&dev));
   const int n2 = d == 3 ? n[2] : 1;
@@ -343,32 +629,17 @@ scfft_status get_plan(int d, const int* n, int prec, int nsolve, bool st, int sy
     *out = it->second;
     return SCFFT_OK;
   }
+  Knobs want;
+  bool tuned = false;
+  scfft_status rc = knobs_for(dev, d, n, prec, st, symbol, real, tc, stream, &want, &tuned);
+  if (rc != SCFFT_OK) return rc;
   Plan* p = new Plan();
-  plan_shape(p, dev, d, n, prec, nsolve, st, symbol, real);
-  const size_t xfield = p->xbytes, rfield = p->rbytes;
-  auto fail = [&](hipError_t e) {
+  plan_shape(p, dev, d, n, prec, nsolve, st, symbol, real, want);
+  p->tuned = tuned;
+  rc = plan_alloc(p, stream);
+  if (rc != SCFFT_OK) {
     free_plan(p);
-    return e == hipErrorOutOfMemory ? SCFFT_ERR_OOM : SCFFT_ERR_DEVICE;
-  };
-  hipError_t e;
-  if ((e = hipMalloc(&p->X, xfield)) != hipSuccess) return fail(e);
-  if ((e = hipMalloc(&p->Ep, rfield)) != hipSuccess) return fail(e);
-  if (st) {
-    if ((e = hipMalloc(&p->S, rfield)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc(&p->T, rfield)) != hipSuccess) return fail(e);
-  }
-  if ((e = hipMalloc(&p->part, sizeof(double) * 5 * (size_t)nsolve * d * p->xblocks)) != hipSuccess)
-    return fail(e);
-  if ((e = hipMalloc(&p->ctl, sizeof(SolveCtl) * nsolve)) != hipSuccess) return fail(e);
-  if ((e = hipMalloc(&p->coef, sizeof(SolveCoef) * nsolve)) != hipSuccess) return fail(e);
-  for (int a = 0; a < d; ++a) {
-    if ((e = hipMalloc(&p->tw[a], p->esz * n[a])) != hipSuccess) return fail(e);
-    if ((e = hipMalloc(&p->sym[a], 2 * sizeof(double) * n[a])) != hipSuccess) return fail(e);
-  }
-  if (plan_tables(p, stream) != SCFFT_OK) return fail(hipErrorLaunchFailure);
-  if (ensure_hist(p, 64) != SCFFT_OK) {
-    free_plan(p);
-    return SCFFT_ERR_OOM;
+    return rc;
   }
   g_plans[key] = p;
   *out = p;
@@ -581,9 +852,9 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     rec(0);
     const dim3 grid(p->xblocks, d, p->nsolve);
     if (p->real) {
-      launch_xpass_real<T>(a, grid, st, p->n[0], p->mk, p->nt);
+      launch_xpass_real<T>(a, grid, st, p->n[0], p->mk, p->nt, p->kn.xr);
     } else if (p->p2x) {
-      launch_xpass_reg<T>(a, grid, st, p->n[0], p->mk);
+      launch_xpass_reg<T>(a, grid, st, p->n[0], p->mk, p->kn.xr);
     } else {
       const size_t lds =
           std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
@@ -629,7 +900,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(4);
     if (p->p2y) {
-      launch_line_reg<T, 1>(y, grid, st, p->n[1]);
+      launch_line_reg<T, 1>(y, grid, st, p->n[1], 8);
     } else {
       launch_line_generic<T>(y, grid, (size_t)p->n[1] * p->yC * esz, st);
     }
@@ -645,13 +916,13 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     q.mode = 0;
     q.fin = 1;
     dim3 grid((p->H + p->gC - 1) / p->gC, d == 3 ? p->n[1] : 1, p->nsolve);
-    if ((p->r16g || p->p2g) && q.fin) grid.x += 1;   // the finalizing workgroups
+    if (p->p2g && q.fin) grid.x += 1;   // the finalizing workgroups
     rec(6);
-    if (p->r16g) {
+    if (p->p2g && p->kn.gr == 16) {
       if constexpr (sizeof(T) == 8) launch_line_r16_f64_2048(q, grid, st);
     } else if (p->p2g) {
-      if (d == 2) launch_line_reg<T, 2>(q, grid, st, nl);
-      else launch_line_reg<T, 3>(q, grid, st, nl);
+      if (d == 2) launch_line_reg<T, 2>(q, grid, st, nl, p->kn.gr);
+      else launch_line_reg<T, 3>(q, grid, st, nl, 8);
     } else {
       launch_line_generic<T>(q, grid, (size_t)nl * d * p->gC * esz, st);
     }
@@ -667,7 +938,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     const dim3 grid((p->H + p->yC - 1) / p->yC, p->n[2], p->nsolve * d);
     rec(8);
     if (p->p2y) {
-      launch_line_reg<T, 1>(y, grid, st, p->n[1]);
+      launch_line_reg<T, 1>(y, grid, st, p->n[1], 8);
     } else {
       launch_line_generic<T>(y, grid, (size_t)p->n[1] * p->yC * esz, st);
     }
@@ -954,6 +1225,10 @@ scfft_status read_result(Plan* p, int solve, const scfft_problem* prob, scfft_re
   return (scfft_status)c.status;
 }
 
+long long voxels(const scfft_problem* p) {
+  return (long long)p->n[0] * p->n[1] * (p->d == 3 ? p->n[2] : 1);
+}
+
 bool bad_e0(const scfft_problem* p) {
   double n2 = 0;
   for (int i = 0; i < p->d; ++i) {
@@ -1098,16 +1373,18 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
   Plan* p = nullptr;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n));
-  if (rc != SCFFT_OK) return rc;
-  rc = ensure_hist(p, opt->max_iter + 1);
-  if (rc != SCFFT_OK) return rc;
   SolveCtl c;
   SolveCoef cf;
   fill_ctl(c, *opt, sp.kind, prob->d, prob->e0);
-  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
-  p->mk = map_kind(sp.kind, prob->density != nullptr);
+  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)voxels(prob));
+  const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c, &cf, prob->phase,
+                   prob->density};
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, opt->max_iter + 1);
+  if (rc != SCFFT_OK) return rc;
+  p->mk = tc.mk;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);
@@ -1116,6 +1393,32 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   rc = run_loop({p}, {prob->phase}, {prob->density}, opt->max_iter, opt->check_every, st, &ms);
   if (rc != SCFFT_OK) return rc;
   return read_result(p, 0, prob, res, st, ms);
+}
+
+scfft_status scfft_plan_info(const scfft_problem* prob, const scfft_options* opt, int* info,
+                             int cap) {
+  if (!prob || !opt || !info || cap < 10) return SCFFT_ERR_INVALID_ARG;
+  SolveSpec sp{};
+  scfft_status rc = prepare(prob, opt, cd(prob->sigma1.re, prob->sigma1.im), &sp);
+  if (rc != SCFFT_OK) return rc;
+  if (prob->density && !opt->sigma0_set) sp.s0 = graded_sigma0(opt->scheme, sp.s1);
+  std::lock_guard<std::mutex> lk(g_mutex);
+  hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
+  Plan* p = nullptr;
+  const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
+  SolveCtl c;
+  SolveCoef cf;
+  fill_ctl(c, *opt, sp.kind, prob->d, prob->e0);
+  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)voxels(prob));
+  const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c, &cf, prob->phase,
+                   prob->density};
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
+  const int v[10] = {p->real ? 1 : 0, p->packed ? 1 : 0, p->kn.pitch, p->kn.nt, p->kn.xr,
+                     p->kn.gr, p->gC, p->d == 3 ? p->yC : 0, p->tuned ? 1 : 0, p->xL};
+  for (int i = 0; i < 10; ++i) info[i] = v[i];
+  return SCFFT_OK;
 }
 
 scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_options* opt,
@@ -1132,19 +1435,21 @@ scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_optio
   const int d = prob->d;
   Plan* p = nullptr;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  rc = get_plan(d, prob->n, opt->precision, d, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, d, prob->n));
-  if (rc != SCFFT_OK) return rc;
-  rc = ensure_hist(p, opt->max_iter + 1);
-  if (rc != SCFFT_OK) return rc;
   std::vector<SolveCtl> c(d);
   std::vector<SolveCoef> cf(d);
   for (int j = 0; j < d; ++j) {
     double e0[3] = {0.0, 0.0, 0.0};
     e0[j] = 1.0;
     fill_ctl(c[j], *opt, sp.kind, d, e0);
-    fill_coef(cf[j], sp, prob->density != nullptr, d, e0, (double)p->M);
+    fill_coef(cf[j], sp, prob->density != nullptr, d, e0, (double)voxels(prob));
   }
+  const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c[0], &cf[0], prob->phase,
+                   prob->density};
+  rc = get_plan(d, prob->n, opt->precision, d, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, opt->max_iter + 1);
+  if (rc != SCFFT_OK) return rc;
   p->mk = map_kind(sp.kind, prob->density != nullptr);
   SCFFT_HIP(hipMemcpyAsync(p->ctl, c.data(), sizeof(SolveCtl) * d, hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, cf.data(), sizeof(SolveCoef) * d, hipMemcpyHostToDevice, st));
@@ -1184,15 +1489,10 @@ scfft_status scfft_series_coefficients(const scfft_problem* prob, const scfft_op
   std::lock_guard<std::mutex> lk(g_mutex);
   hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
   Plan* p = nullptr;
-  rc = get_plan(prob->d, prob->n, o.precision, 1, true, o.symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n));
-  if (rc != SCFFT_OK) return rc;
-  rc = ensure_hist(p, nterms + 1);
-  if (rc != SCFFT_OK) return rc;
   SolveCtl c;
   SolveCoef cf;
   fill_ctl(c, o, sp.kind, prob->d, prob->e0);
-  fill_coef(cf, sp, false, prob->d, prob->e0, (double)p->M);
+  fill_coef(cf, sp, false, prob->d, prob->e0, (double)voxels(prob));
   // z = 1 and no source: the local map returns K x, and with s1 = 1,
   // inv1w = -1, p1kap = 2 p1 its "physical field" E = -x + 2 p1 s (phase 1),
   // -x (phase 2) is (K x)_Q, so the reduced <J> = <E> is <(K u)_Q>
@@ -1202,9 +1502,15 @@ scfft_status scfft_series_coefficients(const scfft_problem* prob, const scfft_op
   put(cf.p1kap, 2.0 * sp.sc.p[0]);
   for (int i = 0; i < prob->d; ++i) {
     put(cf.kz_src[i], cd(0.0, 0.0));
-    put(cf.init_src[i], cd((double)p->M * prob->e0[i], 0.0));
+    put(cf.init_src[i], cd((double)voxels(prob) * prob->e0[i], 0.0));
   }
-  p->mk = map_kind(sp.kind, false);
+  const TuneCtx tc{map_kind(sp.kind, false), &c, &cf, prob->phase, nullptr};
+  rc = get_plan(prob->d, prob->n, o.precision, 1, true, o.symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, nterms + 1);
+  if (rc != SCFFT_OK) return rc;
+  p->mk = tc.mk;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);
@@ -1319,19 +1625,22 @@ scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scff
   for (int i = 0; i < nprob; ++i) {
     bool real = true;
     for (int j = 0; j < nsig; ++j) real = real && real_ok(specs[i][j], probs[i].d, probs[i].n);
-    scfft_status rc = get_plan(probs[i].d, probs[i].n, o0.precision, nsig, any_acc, o0.symbol, st,
-                               &plans[i], i, real);
-    if (rc != SCFFT_OK) return rc;
-    rc = ensure_hist(plans[i], o0.max_iter + 1);
-    if (rc != SCFFT_OK) return rc;
     std::vector<SolveCtl> c(nsig);
     std::vector<SolveCoef> cf(nsig);
     for (int j = 0; j < nsig; ++j) {
       fill_ctl(c[j], o0, specs[i][j].kind, probs[i].d, probs[i].e0);
       fill_coef(cf[j], specs[i][j], probs[i].density != nullptr, probs[i].d, probs[i].e0,
-                (double)plans[i]->M);
+                (double)voxels(&probs[i]));
     }
-    plans[i]->mk = map_kind(specs[i][0].kind, probs[i].density != nullptr);
+    // knobs tuned on one solve of this structure
+    const TuneCtx tc{map_kind(specs[i][0].kind, probs[i].density != nullptr), &c[0], &cf[0],
+                     probs[i].phase, probs[i].density};
+    scfft_status rc = get_plan(probs[i].d, probs[i].n, o0.precision, nsig, any_acc, o0.symbol, st,
+                               &plans[i], i, real, &tc);
+    if (rc != SCFFT_OK) return rc;
+    rc = ensure_hist(plans[i], o0.max_iter + 1);
+    if (rc != SCFFT_OK) return rc;
+    plans[i]->mk = tc.mk;
     for (int j = 1; j < nsig; ++j)
       if (map_kind(specs[i][j].kind, probs[i].density != nullptr) != plans[i]->mk)
         return SCFFT_ERR_INVALID_ARG;
@@ -1370,11 +1679,6 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
   Plan* p = nullptr;
   SolveSpec pw{};
   pw.kind = K_POWER;
-  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 2, false, symbol, st, &p, 0,
-                real_ok(pw, prob->d, prob->n));
-  if (rc != SCFFT_OK) return rc;
-  rc = ensure_hist(p, iters + 2);
-  if (rc != SCFFT_OK) return rc;
   scfft_options o;
   scfft_default_options(&o);
   o.tol = -1.0;
@@ -1389,8 +1693,14 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
     sp.kind = K_POWER;
     sp.power_phase = k == 0 ? 1 : 0;
     fill_ctl(c[k], o, K_POWER, prob->d, e0);
-    fill_coef(cf[k], sp, false, prob->d, e0, (double)p->M);
+    fill_coef(cf[k], sp, false, prob->d, e0, (double)voxels(prob));
   }
+  const TuneCtx tc{MAP_LIN, &c[0], &cf[0], prob->phase, nullptr};
+  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 2, false, symbol, st, &p, 0,
+                real_ok(pw, prob->d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, iters + 2);
+  if (rc != SCFFT_OK) return rc;
   p->mk = MAP_LIN;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, cf, sizeof(cf), hipMemcpyHostToDevice, st));
@@ -1433,9 +1743,6 @@ scfft_status lanczos_run(const scfft_problem* prob, int steps, int symbol, hipSt
   SolveSpec pw{};
   pw.kind = K_POWER;
   pw.power_phase = 1;
-  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 1, false, symbol, st, &p, 0,
-                real_ok(pw, prob->d, prob->n));
-  if (rc != SCFFT_OK) return rc;
   scfft_options o;
   scfft_default_options(&o);
   o.tol = -1.0;
@@ -1445,7 +1752,11 @@ scfft_status lanczos_run(const scfft_problem* prob, int steps, int symbol, hipSt
   SolveCtl c;
   SolveCoef cf;
   fill_ctl(c, o, K_POWER, prob->d, prob->e0);
-  fill_coef(cf, pw, false, prob->d, prob->e0, (double)p->M);
+  fill_coef(cf, pw, false, prob->d, prob->e0, (double)voxels(prob));
+  const TuneCtx tc{MAP_LIN, &c, &cf, prob->phase, nullptr};
+  rc = get_plan(prob->d, prob->n, SCFFT_FP64, 1, false, symbol, st, &p, 0,
+                real_ok(pw, prob->d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
   p->mk = MAP_LIN;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
@@ -1685,8 +1996,18 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
   {
     std::lock_guard<std::mutex> lk(g_mutex);
     Plan* p = nullptr;
+    SolveCtl c0;
+    SolveCoef cf0;
+    {
+      SolveSpec s = sp;
+      s.kind = K_EM;
+      fill_ctl(c0, o, s.kind, prob->d, prob->e0);
+      fill_coef(cf0, s, prob->density != nullptr, prob->d, prob->e0, (double)M);
+    }
+    const TuneCtx tc{map_kind(K_EM, prob->density != nullptr), &c0, &cf0, prob->phase,
+                     prob->density};
     rc = get_plan(prob->d, prob->n, o.precision, 1, false, o.symbol, st, &p, 0,
-                  real_ok(sp, prob->d, prob->n));
+                  real_ok(sp, prob->d, prob->n), &tc);
     if (rc == SCFFT_OK) rc = ensure_hist(p, o.max_iter + 1);
     for (int pass = 0; pass < 2 && rc == SCFFT_OK; ++pass) {
       SolveSpec s = sp;
@@ -1790,19 +2111,21 @@ scfft_status scfft_profile_passes(const scfft_problem* prob, const scfft_options
   hipStream_t st = reinterpret_cast<hipStream_t>(opt->stream);
   Plan* p = nullptr;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n));
-  if (rc != SCFFT_OK) return rc;
-  rc = ensure_hist(p, iters + 2);
-  if (rc != SCFFT_OK) return rc;
   scfft_options o = *opt;
   o.tol = -1;
   o.max_iter = iters + 1;
   SolveCtl c;
   SolveCoef cf;
   fill_ctl(c, o, sp.kind, prob->d, prob->e0);
-  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)p->M);
-  p->mk = map_kind(sp.kind, prob->density != nullptr);
+  fill_coef(cf, sp, prob->density != nullptr, prob->d, prob->e0, (double)voxels(prob));
+  const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c, &cf, prob->phase,
+                   prob->density};
+  rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
+                real_ok(sp, prob->d, prob->n), &tc);
+  if (rc != SCFFT_OK) return rc;
+  rc = ensure_hist(p, iters + 2);
+  if (rc != SCFFT_OK) return rc;
+  p->mk = tc.mk;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
   SCFFT_HIP(hipMemcpyAsync(p->coef, &cf, sizeof(cf), hipMemcpyHostToDevice, st));
   rc = launch_init(p, st);
@@ -1919,8 +2242,14 @@ scfft_status scfft_solve_noalloc(const scfft_problem* prob, const scfft_options*
   if (rc != SCFFT_OK) return rc;
   Plan p;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  plan_shape(&p, dev, prob->d, prob->n, opt->precision, 1, acc, opt->symbol,
-             real_ok(sp, prob->d, prob->n));
+  const bool real = real_ok(sp, prob->d, prob->n);
+  // the knobs scfft_solve tuned for this configuration, if any (tuning itself
+  // would allocate)
+  bool tuned = false;
+  const Knobs kn = cached_knobs(dev, prob->d, prob->n, opt->precision, acc, opt->symbol, real,
+                                map_kind(sp.kind, prob->density != nullptr), &tuned);
+  plan_shape(&p, dev, prob->d, prob->n, opt->precision, 1, acc, opt->symbol, real, kn);
+  p.tuned = tuned;
   const int cap = opt->max_iter + 1;
   if (carve(&p, nullptr, cap) > kScratchBytes) {
     res->status = SCFFT_ERR_INVALID_ARG;

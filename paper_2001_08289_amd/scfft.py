@@ -63,7 +63,7 @@ EXPORTS = ("scfft_default_options", "scfft_solve", "scfft_solve_noalloc", "scfft
            "scfft_estimate_interval",
            "scfft_gradient", "scfft_effective_tensor", "scfft_series_coefficients",
            "scfft_series_evaluate", "scfft_lanczos", "scfft_estimate_interval_lanczos",
-           "scfft_profile_passes", "scfft_scheme_scalars", "scfft_sigma1_from_z",
+           "scfft_profile_passes", "scfft_plan_info", "scfft_scheme_scalars", "scfft_sigma1_from_z",
            "scfft_status_string", "scfft_release", "scfft_version")
 
 
@@ -102,6 +102,8 @@ def load_library(path: str = _LIB_PATH) -> ctypes.CDLL:
     lib.scfft_estimate_interval_lanczos.restype = ctypes.c_int
     lib.scfft_profile_passes.argtypes = [P, O, ctypes.c_int, dp, ctypes.c_int]
     lib.scfft_profile_passes.restype = ctypes.c_int
+    lib.scfft_plan_info.argtypes = [P, O, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
+    lib.scfft_plan_info.restype = ctypes.c_int
     lib.scfft_scheme_scalars.argtypes = [ctypes.c_int, c64, ctypes.c_double, ctypes.c_double,
                                          ctypes.POINTER(c64)]
     lib.scfft_scheme_scalars.restype = ctypes.c_int
@@ -418,6 +420,22 @@ def estimate_interval_lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="ro
         raise ScfftError(rc, "scfft_estimate_interval_lanczos")
     keys = ("alpha", "beta", "alpha_used", "beta_used", "mu_min", "mu_max")
     return {k: x.value for k, x in zip(keys, v)}
+
+
+PLAN_INFO_KEYS = ("real", "packed", "pitch", "nontemporal", "x_radix", "gamma_radix",
+                  "gamma_tile", "y_tile", "tuned", "x_rows")
+
+
+def plan_info(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,
+              precision="fp32", symbol="rotated", alpha=0.25, beta=4.0, stream=None) -> dict:
+    """scfft_plan_info: the execution choices (tuned or by rule) of a solve."""
+    prob, keep = make_problem(phase, density, sigma1, e0)
+    opt = make_options(scheme, precision, symbol, alpha, beta, stream=stream)
+    info = (ctypes.c_int * 10)()
+    rc = _lib.scfft_plan_info(ctypes.byref(prob), ctypes.byref(opt), info, 10)
+    if rc != OK:
+        raise ScfftError(rc, "scfft_plan_info")
+    return dict(zip(PLAN_INFO_KEYS, list(info)))
 
 
 def profile_passes(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,

@@ -69,6 +69,27 @@ def _row(r, **kw):
     return d
 
 
+def batch_inputs(scfft, inputs, torch):
+    """The 16 random-disk structures (seeds 0-15, grids 256..1024) on the
+    device, their contour intervals and the 128 conductivities each."""
+    chis, alphas, betas, sig = [], [], [], []
+    t_est = 0.0
+    for seed, n in enumerate(inputs.BATCH_GRIDS):
+        chi_np, _ = inputs.random_disks(n, seed=seed)
+        chi = torch.as_tensor(chi_np).cuda()
+        t0 = time.perf_counter()
+        e = scfft.estimate_interval(chi, 100)
+        t_est += time.perf_counter() - t0
+        a_u = min(0.8 * e["alpha"], 0.8 / e["beta"], 0.0625)
+        b_u = 1.0 / a_u
+        z = inputs.contour_points(128, 0.6)
+        chis.append(chi)
+        alphas.append(a_u)
+        betas.append(b_u)
+        sig.append([scfft.sigma1_from_z(a_u, b_u, zz) for zz in z])
+    return chis, alphas, betas, sig, t_est
+
+
 def extra_configs(scfft, inputs, torch) -> dict:
     """3D cube array, mixed-grid batched contour sweep, adjoint gradients."""
     out = {}
@@ -180,25 +201,17 @@ def extra_configs(scfft, inputs, torch) -> dict:
 
     # batched sweep: 16 disk microstructures on mixed grids x 128 contour conductivities
     grids = inputs.BATCH_GRIDS
-    chis, alphas, betas, sig = [], [], [], []
-    t_est = 0.0
-    for seed, n in enumerate(grids):
-        chi_np, _ = inputs.random_disks(n, seed=seed)
-        chi = torch.as_tensor(chi_np).cuda()
-        t0 = time.perf_counter()
-        e = scfft.estimate_interval(chi, 100)
-        t_est += time.perf_counter() - t0
-        a_u = min(0.8 * e["alpha"], 0.8 / e["beta"], 0.0625)
-        b_u = 1.0 / a_u
-        z = inputs.contour_points(128, 0.6)
-        chis.append(chi)
-        alphas.append(a_u)
-        betas.append(b_u)
-        sig.append([scfft.sigma1_from_z(a_u, b_u, zz) for zz in z])
+    chis, alphas, betas, sig, t_est = batch_inputs(scfft, inputs, torch)
     scfft.release()
     vox = sum(n * n for n in grids) * 128
     res = {}
-    for prec, tol in (("fp32", 1e-6),):
+    sstar = {}
+    for prec, tol in (("fp32", 1e-6), ("fp64", 1e-8)):
+        # untimed: the first batch call on these grids tunes, plans and
+        # captures them (every solve stops at its first residual here)
+        scfft.solve_batch(chis, np.array(sig), scheme="acc_em", alphas=alphas, betas=betas,
+                          precision=prec, tol=1e300, max_iter=400, check_every=8)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         rs = scfft.solve_batch(chis, np.array(sig), scheme="acc_em", alphas=alphas, betas=betas,
                                precision=prec, tol=tol, max_iter=400, check_every=8)
@@ -206,19 +219,31 @@ def extra_configs(scfft, inputs, torch) -> dict:
         wall = time.perf_counter() - t0
         its = np.array([r["iterations"] for r in rs])
         stats = np.array([r["status"] for r in rs])
+        sstar[prec] = np.array([complex(r["sigma_star"]) for r in rs])
         # every solve is iterated until the slowest of the batch stops; the
         # voxel-iterations counted here are the useful ones (up to each stop)
         useful = sum(n * n * int(its[i * 128:(i + 1) * 128].sum()) for i, n in enumerate(grids))
         hist = {scfft.status_string(int(k)): int((stats == k).sum()) for k in np.unique(stats)}
         flagged = [(int(i) // 128, int(i) % 128) for i in np.nonzero(stats != 0)[0][:8]]
         res[prec] = {"wall_s": round(wall, 3), "useful_voxel_iters_per_s": useful / wall,
+                     "device_ms": round(rs[0]["elapsed_ms"], 3),
                      "iterations_min_mean_max": [int(its.min()), float(its.mean()), int(its.max())],
                      "status_counts": hist,
                      "flagged_examples": [{"structure": a, "j": b, "sigma1": str(np.round(sig[a][b], 4)),
                                            "iterations": int(its[a * 128 + b]),
                                            "residual": rs[a * 128 + b]["residual"]} for a, b in flagged]}
-        log("batch", prec, res[prec])
+        res[prec]["status_codes"] = stats
+        log("batch", prec, {k: v for k, v in res[prec].items() if k != "status_codes"})
         scfft.release()
+    # fp32 sigma* against the fp64 batch, for the solves that converged and
+    # for those that stagnated at the fp32 floor
+    st32 = res["fp32"].pop("status_codes")
+    res["fp64"].pop("status_codes")
+    rel = np.abs(sstar["fp32"] - sstar["fp64"]) / np.abs(sstar["fp64"])
+    res["fp32_vs_fp64_sigma_rel_err"] = {
+        "converged_max": float(rel[st32 == 0].max()) if np.any(st32 == 0) else None,
+        "stagnated_max": float(rel[st32 != 0].max()) if np.any(st32 != 0) else None,
+        "all_median": float(np.median(rel))}
     out["disk_batch"] = {"solves": len(rs), "voxels_per_batch_iteration": vox,
                          "interval_estimate_s": round(t_est, 3), "runs": res,
                          "workload": "16 periodic random-disk microstructures (seeds 0-15, radii "
@@ -265,7 +290,8 @@ def main() -> int:
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the headline iteration with per-kernel timing (for rocprofv3)")
     ap.add_argument("--profile-workload", default="headline",
-                    choices=["headline", "cube256_acc_em_fp32", "square2048_acc_em_fp64"],
+                    choices=["headline", "cube256_acc_em_fp32", "square2048_acc_em_fp64",
+                             "batch_fp32", "batch_fp64"],
                     help="workload of --profile-only")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3D cube, batched-sweep and gradient workloads")
@@ -299,6 +325,17 @@ def main() -> int:
         float(cal_x.sum())
         torch.cuda.synchronize()
         del cal_x
+        if args.profile_workload.startswith("batch"):
+            # the 16 x 128 contour batch, a fixed number of iterations
+            chis, alphas, betas, sig, _ = batch_inputs(scfft, inputs, torch)
+            prec = args.profile_workload.split("_")[1]
+            scfft.solve_batch(chis, np.array(sig), scheme="acc_em", alphas=alphas, betas=betas,
+                              precision=prec, tol=-1.0, max_iter=args.profile_iters,
+                              stag_window=0, div_factor=0.0, check_every=8)
+            torch.cuda.synchronize()
+            print(json.dumps({"workload": args.profile_workload, "iterations": args.profile_iters,
+                              "grids": list(inputs.BATCH_GRIDS)}), flush=True)
+            return 0
         if args.profile_workload == "cube256_acc_em_fp32":
             # 256^3 cube array, sigma1 = 100, the symmetrised power-iteration interval
             chi3 = torch.as_tensor(inputs.cube_array(256)).cuda()

@@ -60,6 +60,7 @@ FftDesc make_desc(int n) {
       m /= r;
     }
   }
+
   return fd;
 }
 
@@ -1068,6 +1069,31 @@ scfft_status work_stream(hipStream_t st, hipStream_t* ws) {
   return SCFFT_OK;
 }
 
+// Streams (default priority) and events that fork and join the parallel
+// branches of a captured batch graph, one set per device.
+constexpr int kBranches = 4;
+struct Branches {
+  hipStream_t s[kBranches];
+  hipEvent_t fork;
+  hipEvent_t join[kBranches];
+};
+std::map<int, Branches> g_branches;
+
+scfft_status branches_for(int dev, Branches** out) {
+  auto it = g_branches.find(dev);
+  if (it == g_branches.end()) {
+    Branches b{};
+    for (int i = 0; i < kBranches; ++i) {
+      SCFFT_HIP(hipStreamCreateWithFlags(&b.s[i], hipStreamNonBlocking));
+      SCFFT_HIP(hipEventCreateWithFlags(&b.join[i], hipEventDisableTiming));
+    }
+    SCFFT_HIP(hipEventCreateWithFlags(&b.fork, hipEventDisableTiming));
+    it = g_branches.emplace(dev, b).first;
+  }
+  *out = &it->second;
+  return SCFFT_OK;
+}
+
 scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const uint8_t*>& phases,
                        const std::vector<const double*>& dens, int ce, hipStream_t ws,
                        hipGraphExec_t* out) {
@@ -1085,11 +1111,44 @@ scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const 
       *out = g.exec;
       return SCFFT_OK;
     }
+  // Several plans (a batch of structures) become parallel branches of the
+  // graph, at most kBranches, each a chain of its plans' iterations; plans
+  // go to the least loaded branch, largest first (cost: voxels x solves).
+  const int nb = (int)std::min<size_t>(plans.size(), kBranches);
+  std::vector<int> branch(plans.size(), 0);
+  if (nb > 1) {
+    std::vector<size_t> order(plans.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      return plans[a]->M * plans[a]->nsolve > plans[b]->M * plans[b]->nsolve;
+    });
+    std::vector<long long> load(nb, 0);
+    for (size_t i : order) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      branch[i] = b;
+      load[b] += plans[i]->M * plans[i]->nsolve;
+    }
+  }
+  Branches* br = nullptr;
+  if (nb > 1) {
+    scfft_status rb = branches_for(plans[0]->dev, &br);
+    if (rb != SCFFT_OK) return rb;
+  }
   SCFFT_HIP(hipStreamBeginCapture(ws, hipStreamCaptureModeThreadLocal));
   scfft_status rc = SCFFT_OK;
+  if (nb > 1) {
+    if (hipEventRecord(br->fork, ws) != hipSuccess) rc = SCFFT_ERR_DEVICE;
+    for (int b = 0; b < nb && rc == SCFFT_OK; ++b)
+      if (hipStreamWaitEvent(br->s[b], br->fork, 0) != hipSuccess) rc = SCFFT_ERR_DEVICE;
+  }
   for (int k = 0; k < ce && rc == SCFFT_OK; ++k)
     for (size_t i = 0; i < plans.size() && rc == SCFFT_OK; ++i)
-      rc = launch_iteration(plans[i], phases[i], dens[i], ws);
+      rc = launch_iteration(plans[i], phases[i], dens[i], nb > 1 ? br->s[branch[i]] : ws);
+  if (nb > 1)
+    for (int b = 0; b < nb && rc == SCFFT_OK; ++b)
+      if (hipEventRecord(br->join[b], br->s[b]) != hipSuccess ||
+          hipStreamWaitEvent(ws, br->join[b], 0) != hipSuccess)
+        rc = SCFFT_ERR_DEVICE;
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(ws, &graph);
   if (rc != SCFFT_OK || e != hipSuccess) {

@@ -394,6 +394,19 @@ def main() -> int:
                 "iteration_frac_kernel_time": round(
                     iter_bytes / ((prof["xpass"] + prof["gamma"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     print(f"# passes {prof}", file=sys.stderr, flush=True)
+    # the autotuner's plan against the built-in rules (tuning off)
+    plan_report = {"tuned": scfft.plan_info(chi, hs["sigma1"], e0, hs["scheme"],
+                                            precision=hs["precision"], alpha=0.25, beta=4.0),
+                   "tuned_pass_ms": {k: round(prof[k], 5) for k in ("xpass", "gamma")}}
+    os.environ["SCFFT_TUNE"] = "0"
+    scfft.release()
+    rule = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=hs["precision"],
+                                alpha=0.25, beta=4.0, iters=args.profile_iters)
+    plan_report["rules"] = scfft.plan_info(chi, hs["sigma1"], e0, hs["scheme"],
+                                           precision=hs["precision"], alpha=0.25, beta=4.0)
+    plan_report["rules_pass_ms"] = {k: round(rule[k], 5) for k in ("xpass", "gamma")}
+    del os.environ["SCFFT_TUNE"]
+    scfft.release()
 
     # ---------------------------------------------------------- sweep
     sweep = []
@@ -421,6 +434,50 @@ def main() -> int:
                 "vs_em": round(t["em"] / t["acc_em"], 3) if "em" in t else None}
 
     accel = {f"{p}@{s}": speedup(p, s) for p in ("fp64", "fp32") for s in SIGMAS} if sweep else {}
+
+    # fp32 at the fp64 run's iteration count: the precision's own cost and
+    # error at equal work (the fp32 rows above stop at a 1e-6 increment)
+    same_iters = []
+    control = {}
+    if not args.no_sweep:
+        fp64_rows = {(r["sigma1"], r["scheme"]): r for r in sweep if r["precision"] == "fp64"}
+        for (s1, scheme), r64 in fp64_rows.items():
+            if r64["status"] != 0:
+                continue
+            r = scfft.solve(chi, s1, e0, scheme, precision="fp32", alpha=0.25, beta=4.0, tol=-1,
+                            max_iter=r64["iterations"], stag_window=0, div_factor=0,
+                            check_every=8, fields=False, history=False)
+            same_iters.append({"sigma1": s1, "scheme": scheme, "iterations": r["iterations"],
+                               "time_ms": round(r["elapsed_ms"], 3),
+                               "fp64_time_ms": r64["time_ms"],
+                               "rel_err_vs_fp64": abs(r["sigma_star"] - r64["sigma_star"]) /
+                               abs(r64["sigma_star"])})
+        # the literal symbol of eq. J11 (spectral) and the resistor network as
+        # controls of the rotated default: 2048^2 to 1e-8 in fp64
+        rows = []
+        for symbol in ("spectral", "network"):
+            for s1 in SIGMAS:
+                for scheme in SCHEMES:
+                    r = scfft.solve(chi, s1, e0, scheme, precision="fp64", alpha=0.25, beta=4.0,
+                                    symbol=symbol, tol=1e-8, max_iter=4000, check_every=32,
+                                    fields=False, history=False, raise_on_error=False)
+                    rows.append({"symbol": symbol, "sigma1": s1, "scheme": scheme,
+                                 "status": r["status"], "iterations": r["iterations"],
+                                 "time_ms": round(r["elapsed_ms"], 3),
+                                 "rel_err_J47a": abs(r["sigma_star"] - exact[s1]) / abs(exact[s1])})
+                    print(f"# control {rows[-1]}", file=sys.stderr, flush=True)
+            scfft.release()
+        control["square_2048_fp64_tol1e-8"] = rows
+        chi64 = torch.as_tensor(inputs.square_array(64)).cuda()
+        ex10 = float(np.sqrt(31.0 / 13.0))
+        c1 = {}
+        for symbol in ("rotated", "spectral", "network"):
+            r = scfft.solve(chi64, 10.0, e0, "ms", precision="fp64", symbol=symbol, tol=1e-10,
+                            max_iter=4000, check_every=1, fields=False, history=False)
+            c1[symbol] = {"iterations": r["iterations"], "sigma_star": r["sigma_star"].real,
+                          "rel_err_J47a": abs(r["sigma_star"] - ex10) / ex10}
+        control["square_64_ms_fp64_tol1e-10"] = c1
+        scfft.release()
 
     # ---------------------------------------------------------- CPU oracle
     cpu = None
@@ -461,6 +518,9 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "speedup_time_to_tol": accel,
+        "fp32_at_fp64_iterations": same_iters,
+        "symbol_controls": control,
+        "plan": plan_report,
         "sweep": sweep,
         "extra_configs": extra,
     }

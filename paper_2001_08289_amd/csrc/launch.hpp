@@ -8,6 +8,7 @@
 #pragma once
 
 #include "kernels_real.hpp"
+#include "kernels_smooth.hpp"
 
 namespace scfft {
 
@@ -62,6 +63,49 @@ int line_tile_max(int n, int esz, int D, int gr);
 
 // fp64 Gamma pass of 2048-point columns with radix-16 register FFTs.
 void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
+
+// Line lengths with compile-time mixed-radix passes (2D full-complex x and
+// Gamma passes); every other 2/3/5-smooth length takes the runtime-planned
+// passes below.
+#define SCFFT_SMOOTH_SWITCH(n, CALL) \
+  switch (n) {                       \
+    case 48: CALL(48);               \
+    case 80: CALL(80);               \
+    case 90: CALL(90);               \
+    case 96: CALL(96);               \
+    case 120: CALL(120);             \
+    case 160: CALL(160);             \
+    case 180: CALL(180);             \
+    case 192: CALL(192);             \
+    case 240: CALL(240);             \
+    case 288: CALL(288);             \
+    case 320: CALL(320);             \
+    case 360: CALL(360);             \
+    case 384: CALL(384);             \
+    case 400: CALL(400);             \
+    case 432: CALL(432);             \
+    case 480: CALL(480);             \
+    case 576: CALL(576);             \
+    case 640: CALL(640);             \
+    case 720: CALL(720);             \
+    case 768: CALL(768);             \
+    case 800: CALL(800);             \
+    case 864: CALL(864);             \
+    case 900: CALL(900);             \
+    case 960: CALL(960);             \
+    default: break;                  \
+  }
+
+// Compile-time mixed-radix passes: false (nothing launched) for a length
+// without an instantiation.  x pass grid = (row blocks of smooth_lines rows,
+// d, solves); Gamma grid = (column tiles of smooth_cols columns, 1, solves).
+template <typename T>
+bool launch_xpass_smooth(const XArgs& a, dim3 grid, hipStream_t st, int n);
+template <typename T>
+bool launch_gamma_smooth(const GArgs& a, dim3 grid, hipStream_t st, int n);
+// Rows per x-pass workgroup and columns per Gamma tile (0: no instantiation).
+int smooth_lines(int n, int esz);
+int smooth_cols(int n, int esz);
 
 // LDS-staged mixed-radix passes (any 2/3/5-smooth length).
 template <typename T>

@@ -72,6 +72,32 @@ int line_tile_max(int n, int esz, int D, int gr) {
   return esz == 8 ? tile_max_r<float>(n, D, gr) : tile_max_r<double>(n, D, gr);
 }
 
+int smooth_lines(int n, int esz) {
+  if (esz == 8) {
+#define C_(N) return sm_lines<float, N>()
+    SCFFT_SMOOTH_SWITCH(n, C_)
+#undef C_
+  } else {
+#define C_(N) return sm_lines<double, N>()
+    SCFFT_SMOOTH_SWITCH(n, C_)
+#undef C_
+  }
+  return 0;
+}
+
+int smooth_cols(int n, int esz) {
+  if (esz == 8) {
+#define C_(N) return sm_cols<float, N>()
+    SCFFT_SMOOTH_SWITCH(n, C_)
+#undef C_
+  } else {
+#define C_(N) return sm_cols<double, N>()
+    SCFFT_SMOOTH_SWITCH(n, C_)
+#undef C_
+  }
+  return 0;
+}
+
 template void launch_xpass_generic<float>(const XArgs&, dim3, size_t, hipStream_t);
 template void launch_xpass_generic<double>(const XArgs&, dim3, size_t, hipStream_t);
 template void launch_line_generic<float>(const GArgs&, dim3, size_t, hipStream_t);

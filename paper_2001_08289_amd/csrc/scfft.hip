@@ -151,6 +151,7 @@ struct Plan {
   int xlines = 0, xL = 1, xblocks = 0;
   int gC = 1, yC = 1;
   bool p2x = false, p2g = false, p2y = false;   // register-resident passes
+  bool smx = false, smg = false;                 // compile-time mixed-radix passes
   Knobs kn;                                      // resolved speed choices
   bool tuned = false;                            // kn came from the autotuner
   int mk = MAP_LIN;                              // local map of the current solves
@@ -238,6 +239,9 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   p->p2g = is_p2(nlast) && !std::getenv("SCFFT_NO_P2") && (d == 2 || nlast <= 1024);
   p->H = real ? n[0] / 2 + 1 : n[0];
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
+  const bool sm_on = !std::getenv("SCFFT_NO_SMOOTH");
+  p->smx = sm_on && !real && !p->p2x && smooth_lines(n[0], esz) > 0;
+  p->smg = sm_on && d == 2 && !p->p2g && smooth_cols(nlast, esz) > 0;
   Knobs& k = p->kn;
   k = Knobs();
   // x pass radix
@@ -246,6 +250,9 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
     if (k.xr != 4 && k.xr != 8) k.xr = rule_xr(n[0], esz);
     if (n[0] < k.xr) k.xr = 4;
     p->xL = xpass_lines(n[0], esz, k.xr);
+  } else if (p->smx) {
+    k.xr = 0;
+    p->xL = smooth_lines(n[0], esz);
   } else {
     k.xr = 0;
     p->xL = std::max(1, std::min(el / n[0], p->xlines));
@@ -263,6 +270,9 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
     const int c = env_int("SCFFT_LINE_C", want.gC ? want.gC : cmax);
     k.gC = (c == 1 || c == 2 || c == 4 || c == 8) ? std::min(c, cmax) : cmax;
     if (k.gr == 16) k.gC = cmax;   // one instantiation: the widest tile
+  } else if (p->smg) {
+    k.gr = 0;
+    k.gC = smooth_cols(nlast, esz);   // fixed by the instantiation
   } else {
     k.gr = 0;
     const int cmax = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
@@ -479,6 +489,8 @@ scfft_status autotune(int dev, int d, const int* n, int prec, bool st, int symbo
       }
       for (int c = 1; c <= std::min(cmax, 8); c *= 2) gcs.push_back({r, c});
     }
+  } else if (probe.smg) {
+    gcs.push_back({0, probe.gC});
   } else {
     const int el = elems_for(prec);
     const int cmax = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
@@ -856,6 +868,8 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
       launch_xpass_real<T>(a, grid, st, p->n[0], p->mk, p->nt, p->kn.xr);
     } else if (p->p2x) {
       launch_xpass_reg<T>(a, grid, st, p->n[0], p->mk, p->kn.xr);
+    } else if (p->smx) {
+      if (!launch_xpass_smooth<T>(a, grid, st, p->n[0])) return SCFFT_ERR_DEVICE;
     } else {
       const size_t lds =
           std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
@@ -924,6 +938,8 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     } else if (p->p2g) {
       if (d == 2) launch_line_reg<T, 2>(q, grid, st, nl, p->kn.gr);
       else launch_line_reg<T, 3>(q, grid, st, nl, 8);
+    } else if (p->smg) {
+      if (!launch_gamma_smooth<T>(q, grid, st, nl)) return SCFFT_ERR_DEVICE;
     } else {
       launch_line_generic<T>(q, grid, (size_t)nl * d * p->gC * esz, st);
     }
@@ -1474,9 +1490,10 @@ scfft_status scfft_plan_info(const scfft_problem* prob, const scfft_options* opt
   rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
                 real_ok(sp, prob->d, prob->n), &tc);
   if (rc != SCFFT_OK) return rc;
-  const int v[10] = {p->real ? 1 : 0, p->packed ? 1 : 0, p->kn.pitch, p->kn.nt, p->kn.xr,
-                     p->kn.gr, p->gC, p->d == 3 ? p->yC : 0, p->tuned ? 1 : 0, p->xL};
-  for (int i = 0; i < 10; ++i) info[i] = v[i];
+  const int v[12] = {p->real ? 1 : 0, p->packed ? 1 : 0, p->kn.pitch, p->kn.nt, p->kn.xr,
+                     p->kn.gr, p->gC, p->d == 3 ? p->yC : 0, p->tuned ? 1 : 0, p->xL,
+                     p->p2x ? 1 : p->smx ? 2 : 0, p->p2g ? 1 : p->smg ? 2 : 0};
+  for (int i = 0; i < std::min(cap, 12); ++i) info[i] = v[i];
   return SCFFT_OK;
 }
 

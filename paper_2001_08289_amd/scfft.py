@@ -423,7 +423,7 @@ def estimate_interval_lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="ro
 
 
 PLAN_INFO_KEYS = ("real", "packed", "pitch", "nontemporal", "x_radix", "gamma_radix",
-                  "gamma_tile", "y_tile", "tuned", "x_rows")
+                  "gamma_tile", "y_tile", "tuned", "x_rows", "x_engine", "gamma_engine")
 
 
 def plan_info(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,
@@ -431,8 +431,8 @@ def plan_info(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, d
     """scfft_plan_info: the execution choices (tuned or by rule) of a solve."""
     prob, keep = make_problem(phase, density, sigma1, e0)
     opt = make_options(scheme, precision, symbol, alpha, beta, stream=stream)
-    info = (ctypes.c_int * 10)()
-    rc = _lib.scfft_plan_info(ctypes.byref(prob), ctypes.byref(opt), info, 10)
+    info = (ctypes.c_int * len(PLAN_INFO_KEYS))()
+    rc = _lib.scfft_plan_info(ctypes.byref(prob), ctypes.byref(opt), info, len(PLAN_INFO_KEYS))
     if rc != OK:
         raise ScfftError(rc, "scfft_plan_info")
     return dict(zip(PLAN_INFO_KEYS, list(info)))

@@ -1,0 +1,90 @@
+"""Compile-time mixed-radix passes (2/3/5-smooth lengths, full-complex 2D).
+
+Every field value after a few fixed iterations against the oracle, on grids
+whose two axes are instantiated lengths (radix sequences with 8, 4, 2, 5
+and 3 passes, several tiles and a ragged last tile of columns and rows), in
+both precisions; and, at the batch grids' own sizes, the same iterations
+against the runtime-planned passes (oracle-pinned elsewhere) with the plan
+report showing which engine ran.
+"""
+import numpy as np
+import pytest
+
+from oracle import solver as osolver
+from paper_2001_08289_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2001_08289_amd import scfft  # noqa: E402
+
+SMOOTH = 2   # plan_info engine code of the compile-time mixed-radix passes
+
+
+def _rel(got, ref):
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.fixture
+def env(monkeypatch):
+    for k in ("SCFFT_NO_SMOOTH", "SCFFT_NO_P2", "SCFFT_LINE_C", "SCFFT_TUNE"):
+        monkeypatch.delenv(k, raising=False)
+    scfft.release()
+    yield monkeypatch
+    scfft.release()
+
+
+@pytest.mark.parametrize("shape", [(48, 80), (90, 96), (120, 160), (180, 90), (240, 192),
+                                   (360, 288)])
+@pytest.mark.parametrize("scheme,s1", [("acc_em", 3 + 2j), ("ms", 10.0), ("em", -5 + 1j),
+                                       ("acc_ms", 100.0)])
+def test_smooth_passes_match_oracle(shape, scheme, s1, env):
+    chi = inputs.random_phase(shape, 0.3, seed=21)
+    if scheme == "em" and shape != (90, 96):
+        pytest.skip("one grid per scheme beyond the accelerated ones")
+    ref = osolver.solve(chi, s1, [1.0, 0.0], scheme, alpha=0.25, beta=4.0, tol=-1, max_iter=3,
+                        stag_window=0, div_factor=0)
+    info = scfft.plan_info(chi, s1, (1, 0), scheme, precision="fp64")
+    assert info["x_engine"] == SMOOTH and info["gamma_engine"] == SMOOTH, info
+    for precision, bound in (("fp64", 1e-11), ("fp32", 2e-6)):
+        got = scfft.solve(chi, s1, (1, 0), scheme, precision=precision, tol=-1, max_iter=3,
+                          stag_window=0, div_factor=0)
+        assert _rel(got["E"].cpu().numpy(), ref["E"]) < bound, (precision, shape)
+        assert _rel(got["J"].cpu().numpy(), ref["J"]) < bound, (precision, shape)
+        assert abs(got["sigma_star"] - ref["sigma_star"]) / abs(ref["sigma_star"]) < bound
+
+
+@pytest.mark.parametrize("n", [288, 400, 576, 720, 900])
+def test_smooth_matches_runtime_planned_passes(n, env):
+    chi = inputs.random_phase((n, n), 0.25, seed=22)
+    out = {}
+    for flag in (None, "1"):
+        if flag:
+            env.setenv("SCFFT_NO_SMOOTH", flag)
+        else:
+            env.delenv("SCFFT_NO_SMOOTH", raising=False)
+        scfft.release()
+        info = scfft.plan_info(chi, 2 + 3j, (1, 0), "acc_em", precision="fp64")
+        assert info["x_engine"] == (0 if flag else SMOOTH), info
+        r = scfft.solve(chi, 2 + 3j, (1, 0), "acc_em", precision="fp64", tol=-1, max_iter=4,
+                        stag_window=0, div_factor=0)
+        out[flag] = r["E"].cpu().numpy()
+    assert _rel(out[None], out["1"]) < 1e-12
+
+
+def test_smooth_batch_of_mixed_grids(env):
+    # one batch over two instantiated sizes and one power of two, each solve
+    # against its own single solve
+    chis = [inputs.random_phase((n, n), 0.3, seed=23 + n) for n in (96, 160, 128)]
+    sig = np.array([[3 + 1j, 0.5 - 2j]] * 3)
+    res = scfft.solve_batch([torch.as_tensor(c).cuda() for c in chis], sig, scheme="acc_em",
+                            precision="fp64", tol=1e-10, max_iter=400)
+    for i, c in enumerate(chis):
+        for j in range(2):
+            one = scfft.solve(c, sig[i, j], (1, 0), "acc_em", precision="fp64", tol=1e-10,
+                              max_iter=400, fields=False)
+            got = res[i * 2 + j]["sigma_star"]
+            assert abs(got - one["sigma_star"]) / abs(one["sigma_star"]) < 1e-12

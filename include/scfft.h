@@ -183,7 +183,10 @@ scfft_status scfft_solve_noalloc(const scfft_problem* prob, const scfft_options*
  * results (host) receives nprob*nsig entries, problem-major (their E/J
  * pointers, if set, must each hold one field).  Every solve keeps its own
  * stop status; finished solves are skipped by the remaining iterations.
- * prob[i].sigma1 is ignored.  Returns the worst status. */
+ * The problems' iteration chains run as up to 4 parallel branches of one
+ * replayed HIP graph (largest first onto the least loaded branch;
+ * SCFFT_BRANCHES=1..4 caps the count).  prob[i].sigma1 is ignored.  Returns
+ * the worst status. */
 scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs,
                                const scfft_options* opts, int nsig,
                                const scfft_c64* sigma1s, scfft_result* results);

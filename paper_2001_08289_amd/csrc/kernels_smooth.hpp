@@ -1,24 +1,25 @@
 // Compile-time mixed-radix passes for 2/3/5-smooth line lengths (gfx950).
 //
-// The same LDS-staged Stockham transform as the runtime-planned passes of
-// device_fft.hpp, but with the line length, the radix sequence, the lines per
-// workgroup and the tile width fixed at compile time: every pass is unrolled,
-// and the index arithmetic of the butterflies (divisions by the butterfly
-// count, the stride and the tile width) folds into multiplications by
-// constants instead of runtime integer divisions.  One instantiation per
-// supported length (SCFFT_SMOOTH_SWITCH); other smooth lengths keep the
-// runtime-planned passes.
+// Each line is transformed by one wave (64 lanes) through its own LDS slot,
+// so the Stockham passes synchronise only the wave (an in-order LDS queue
+// plus a compiler fence), never the workgroup; the line length, the radix
+// sequence and the slot layout are compile-time constants, so every pass is
+// unrolled and its index arithmetic folds into multiplications by constants.
+// Workgroup barriers remain only where waves exchange data: the staging of
+// the strided Gamma tile (coalesced row segments) and the Gamma step, which
+// couples the components of one mode.  One instantiation per supported length
+// (SCFFT_SMOOTH_SWITCH); other smooth lengths keep the runtime-planned
+// passes.
+//
+// Stockham pass p with radix r and stride NS (product of the earlier radices)
+// maps butterfly j (0 <= j < N/r) from inputs j + q N/r to outputs
+// (j div NS) NS r + (j mod NS) + q NS after twiddles exp(-+2 pi i (j mod NS)
+// q / (NS r)); unnormalised, forward exp(-2 pi i jk/N).
 #pragma once
 
 #include "kernels_p2.hpp"
 
 namespace scfft {
-
-constexpr int kSmNT = 1024;   // threads per workgroup
-
-// Elements one workgroup holds in LDS (64 KiB in both precisions).
-template <typename T>
-constexpr int sm_elems() { return sizeof(T) == 4 ? 8192 : 4096; }
 
 // Radix of pass p for a length n: radix 8 while 8 divides, then one radix 4
 // or 2 for the rest of the power of two, then the fives, then the threes;
@@ -53,48 +54,66 @@ constexpr int sm_radix(int n, int p) {
   return 0;
 }
 
-// x pass: whole lines per workgroup; Gamma pass (2D): columns per tile.
-template <typename T, int N>
-constexpr int sm_lines() { return sm_elems<T>() / N; }
-template <typename T, int N>
-constexpr int sm_cols() {
-  return sm_elems<T>() / (2 * N) > 16 ? 16 : sm_elems<T>() / (2 * N);
+// Orders this wave's LDS accesses: every lane's earlier reads and writes
+// are complete (and visible to the wave) before any later one.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One radix-r pass (stride NS) over NL lines of N points in LDS; line l's
-// element k sits at l*LS + k*ES.  LF: consecutive butterflies walk the lines
-// first (the strided tile layout), else the points of one line first.
-template <typename T, int N, int NL, bool LF, int P, int NS>
-__device__ __forceinline__ void sm_pass(cx<T>* __restrict__ lds, const cx<T>* __restrict__ tw,
-                                        T sign, int tid) {
+// Per-length layout: a line's slot holds N points plus a pad that puts
+// consecutive slots one bank apart (slot stride = 1 mod 64 banks per point).
+template <typename T, int N>
+struct SmShape {
+  static constexpr int DW = (int)sizeof(cx<T>) / 4;   // dwords per point
+  static constexpr int Q = 64 / DW;                  // points per bank sweep
+  static constexpr int LSP = (N + Q - 2) / Q * Q + 1;
+  static constexpr int R0 = sm_radix(N, 0);          // radix of the first pass
+  static constexpr int B0 = (N / R0 + 63) / 64;      // its butterflies per lane
+  // x pass: rows (waves) per workgroup; Gamma pass: columns per tile, one
+  // wave per column and component
+  static constexpr int XW = 4;
+  static constexpr int C = sizeof(T) == 4 ? 4 : 2;
+  static constexpr int GW = 2 * C;
+  static constexpr int XLDS = XW * LSP * (int)sizeof(cx<T>) + 5 * XW * 8;
+  static constexpr int GLDS = GW * LSP * (int)sizeof(cx<T>);
+};
+
+// One radix-r pass of a wave's line (slot: N points at slot[0..N)).  P = 0
+// takes its inputs from the registers v0 (point j + q N/R0 of butterfly
+// j = lane + 64 u at v0[u][q]); every pass writes its outputs to the slot.
+template <typename T, int N, int P, int NS>
+__device__ __forceinline__ void sm_pass(const cx<T> (&v0)[SmShape<T, N>::B0][SmShape<T, N>::R0],
+                                        cx<T>* __restrict__ slot, const cx<T>* __restrict__ tw,
+                                        T sign, int lane) {
   if constexpr (NS < N) {
     constexpr int r = sm_radix(N, P);
     static_assert(r > 0 && N % (NS * r) == 0, "radix sequence must factor N");
-    constexpr int NBL = N / r;          // butterflies per line
-    constexpr int NB = NL * NBL;        // butterflies per workgroup
-    constexpr int BPT = (NB + kSmNT - 1) / kSmNT;
-    constexpr int STEP = N / (NS * r);  // twiddle table stride
-    constexpr int LS = LF ? 1 : N;
-    constexpr int ES = LF ? NL : 1;
-    cx<T> v[BPT][r];
+    constexpr int NBL = N / r;                  // butterflies
+    constexpr int BPL = (NBL + 63) / 64;        // per lane
+    constexpr int STEP = N / (NS * r);          // twiddle table stride
+    cx<T> v[BPL][r];
+    if constexpr (P == 0) {
 #pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-      const int b = tid + u * kSmNT;
-      if (NB % kSmNT == 0 || b < NB) {
-        const int l = LF ? b % NL : b / NBL;
-        const int j = LF ? b / NL : b - (b / NBL) * NBL;
-        const cx<T>* base = lds + l * LS;
+      for (int u = 0; u < BPL; ++u)
 #pragma unroll
-        for (int q = 0; q < r; ++q) v[u][q] = base[(j + q * NBL) * ES];
+        for (int q = 0; q < r; ++q) v[u][q] = v0[u][q];
+    } else {
+#pragma unroll
+      for (int u = 0; u < BPL; ++u) {
+        const int j = lane + 64 * u;
+        if (NBL % 64 == 0 || j < NBL) {
+#pragma unroll
+          for (int q = 0; q < r; ++q) v[u][q] = slot[j + q * NBL];
+        }
       }
     }
-    __syncthreads();
+    wave_sync();   // the pass's reads are done before its in-place writes
 #pragma unroll
-    for (int u = 0; u < BPT; ++u) {
-      const int b = tid + u * kSmNT;
-      if (NB % kSmNT == 0 || b < NB) {
-        const int l = LF ? b % NL : b / NBL;
-        const int j = LF ? b / NL : b - (b / NBL) * NBL;
+    for (int u = 0; u < BPL; ++u) {
+      const int j = lane + 64 * u;
+      if (NBL % 64 == 0 || j < NBL) {
         const int k = j % NS;
         if constexpr (NS > 1) {
           // one table load per butterfly; the powers w^q follow by products
@@ -109,132 +128,182 @@ __device__ __forceinline__ void sm_pass(cx<T>* __restrict__ lds, const cx<T>* __
         }
         Dft<T, r>::run(v[u], sign);
         const int idxd = (j / NS) * NS * r + k;
-        cx<T>* base = lds + l * LS;
 #pragma unroll
-        for (int q = 0; q < r; ++q) base[(idxd + q * NS) * ES] = v[u][q];
+        for (int q = 0; q < r; ++q) slot[idxd + q * NS] = v[u][q];
       }
     }
-    __syncthreads();
-    sm_pass<T, N, NL, LF, P + 1, NS * r>(lds, tw, sign, tid);
+    wave_sync();
+    sm_pass<T, N, P + 1, NS * r>(v0, slot, tw, sign, lane);
   }
 }
 
-// Unnormalised transform of NL lines in LDS (callers synchronise before;
-// the last pass ends with a barrier).  sign -1 forward, +1 inverse.
-template <typename T, int N, int NL, bool LF>
-__device__ __forceinline__ void sm_fft(cx<T>* lds, const cx<T>* tw, T sign, int tid) {
-  sm_pass<T, N, NL, LF, 0, 1>(lds, tw, sign, tid);
+// Unnormalised transform of one line held by a wave: input in registers in
+// the first pass's layout, output in the slot in natural order (sign -1
+// forward, +1 inverse).
+template <typename T, int N>
+__device__ __forceinline__ void sm_fft(const cx<T> (&v0)[SmShape<T, N>::B0][SmShape<T, N>::R0],
+                                       cx<T>* slot, const cx<T>* tw, T sign, int lane) {
+  sm_pass<T, N, 0, 1>(v0, slot, tw, sign, lane);
 }
 
-// x pass of a full-complex field (the runtime-planned xpass_kernel with the
-// row length N and NL rows per workgroup fixed): inverse x-FFT, local map of
-// the scheme, forward x-FFT, per-workgroup fp64 partial sums.
-template <typename T, int N>
-__global__ __launch_bounds__(kSmNT) void xpass_sm_kernel(XArgs a) {
-  constexpr int NL = sm_lines<T, N>();
+// x pass of a full-complex field: one row per wave, XW rows per workgroup
+// (rows past the field's last transform zeros and are not stored): inverse
+// x-FFT, local map of the scheme (MK fixes it at compile time), forward
+// x-FFT, fp64 partial sums.
+template <typename T, int N, int MK>
+__global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArgs a) {
+  using SH = SmShape<T, N>;
+  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0;
   const int solve = blockIdx.z;
   const int comp = blockIdx.y;
-  SolveCtl* ctl = a.ctl + solve;
-  if (!a.ignore_done && ctl->done) return;
+  if (!a.ignore_done && a.ctl[solve].done) return;
   extern __shared__ unsigned char smem_raw[];
-  cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x;
-  const long long line0 = (long long)blockIdx.x * NL;
-  const int nl = (int)min((long long)NL, (long long)a.nlines - line0);
-  const int cnt = nl * N;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  cx<T>* slot = reinterpret_cast<cx<T>*>(smem_raw) + w * SH::LSP;
+  double* red = reinterpret_cast<double*>(smem_raw + SH::XW * SH::LSP * sizeof(cx<T>));
+  const long long line = (long long)blockIdx.x * SH::XW + w;
+  const bool valid = line < a.nlines;
   const long long fbase = ((long long)solve * a.d + comp) * a.M;
-  const long long base = line0 * N;
+  const long long base = line * N;
   cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + fbase;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  // rows past the field's last one (tail workgroup) transform zeros
-  for (int i = tid; i < NL * N; i += kSmNT) lds[i] = i < cnt ? X[base + i] : mk<T>(0, 0);
-  __syncthreads();
-  sm_fft<T, N, NL, false>(lds, tw, (T)1, tid);
-  LocalMap<T> lm;
+  cx<T> v0[B0][R0];
+#pragma unroll
+  for (int u = 0; u < B0; ++u) {
+    const int j = lane + 64 * u;
+#pragma unroll
+    for (int q = 0; q < R0; ++q)
+      v0[u][q] = (valid && (NB0 % 64 == 0 || j < NB0)) ? X[base + j + q * NB0] : mk<T>(0, 0);
+  }
+  LocalMap<T, MK> lm;
   lm.load(a, solve, comp, fbase);
+  // the phase map and E_prev do not depend on the FFT: load them first when
+  // the registers allow (at most 16 fp32 / 8 fp64 points per lane)
+  constexpr bool PF = (MK == MAP_LIN || MK == MAP_ACC_EM || MK == MAP_ACC_MS) &&
+                      B0 * R0 * (int)sizeof(cx<T>) <= 128;
+  bool ph[PF ? B0 : 1][PF ? R0 : 1];
+  cx<T> epo[PF ? B0 : 1][PF ? R0 : 1];
+  if (PF && valid) {
+#pragma unroll
+    for (int u = 0; u < B0; ++u) {
+      const int j = lane + 64 * u;
+      if (NB0 % 64 == 0 || j < NB0) {
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          const long long g = base + j + q * NB0;
+          ph[PF ? u : 0][PF ? q : 0] = lm.phase[g] != 0;
+          epo[PF ? u : 0][PF ? q : 0] = lm.Ep[g];
+        }
+      }
+    }
+  }
+  sm_fft<T, N>(v0, slot, tw, (T)1, lane);
   Acc acc;
-  for (int i = tid; i < cnt; i += kSmNT) lds[i] = lm.apply(lds[i], base + i, acc);
-  __syncthreads();
-  sm_fft<T, N, NL, false>(lds, tw, (T)-1, tid);
-  for (int i = tid; i < cnt; i += kSmNT) X[base + i] = lds[i];
-  // deterministic workgroup reduction (wave64 shuffles, then across waves)
-  double v[5] = {acc.Jr, acc.Ji, acc.e2, acc.d2, acc.eJ};
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double s = v[k];
+  for (int u = 0; u < B0; ++u) {
+    const int j = lane + 64 * u;
+    if (valid && (NB0 % 64 == 0 || j < NB0)) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    v[k] = s;
+      for (int q = 0; q < R0; ++q) {
+        const long long g = base + j + q * NB0;
+        v0[u][q] = PF ? lm.apply_pf(slot[j + q * NB0], g, ph[PF ? u : 0][PF ? q : 0],
+                                    epo[PF ? u : 0][PF ? q : 0], acc)
+                      : lm.apply(slot[j + q * NB0], g, acc);
+        acc_settle<true>(acc);
+      }
+    }
   }
-  __syncthreads();   // every thread has stored its outputs: the LDS is free
-  double* red = reinterpret_cast<double*>(smem_raw);   // [5][kSmNT/64]
-  const int lane = tid & 63, wave = tid >> 6;
-  if (lane == 0) {
+  sm_fft<T, N>(v0, slot, tw, (T)-1, lane);
+  if (valid) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) red[k * (kSmNT / 64) + wave] = v[k];
+    for (int t = 0; t < (N + 63) / 64; ++t) {
+      const int i = lane + 64 * t;
+      if (N % 64 == 0 || i < N) X[base + i] = slot[i];
+    }
   }
-  __syncthreads();
-  if (tid < 5) {
-    double s = 0;
-    for (int w = 0; w < kSmNT / 64; ++w) s += red[tid * (kSmNT / 64) + w];
-    a.part[(((long long)solve * a.d + comp) * 5 + tid) * gridDim.x + blockIdx.x] = s;
-  }
+  block_reduce5<64 * SH::XW>(acc, red,
+                             a.part + ((long long)solve * a.d + comp) * 5 * gridDim.x + blockIdx.x,
+                             gridDim.x, tid);
 }
 
-// Gamma pass of a 2D full-complex field (the runtime-planned
-// line_pass_kernel in mode 0 with the column length N and the tile width C
-// fixed): forward y-FFT of both components of C adjacent columns, Gamma_1 of
-// eq. J11 (J44-J45 in H'') with the scheme's k = 0 source, inverse y-FFT.
-// LDS layout [k][line], line = comp*C + l.  Workgroup (0, 0) of each solve
-// also reduces the x pass's partial sums and applies the stop rules.
+// Gamma pass of a 2D full-complex field: a tile of C adjacent columns, one
+// wave per column and component.  The tile is staged through LDS in row
+// segments; each wave runs the forward y-FFT of its line; Gamma_1 of eq. J11
+// (J44-J45 in H'') with the scheme's k = 0 source couples the two components
+// of every mode; each wave runs the inverse y-FFT; the tile is stored back.
+// Workgroup 0 of each solve also reduces the x pass's partial sums and
+// applies the stop rules.
 template <typename T, int N>
-__global__ __launch_bounds__(kSmNT) void gamma_sm_kernel(GArgs a) {
-  constexpr int C = sm_cols<T, N>();
-  constexpr int W = 2 * C;
+__global__ __launch_bounds__((64 * SmShape<T, N>::GW)) void gamma_sm_kernel(GArgs a) {
+  using SH = SmShape<T, N>;
+  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, C = SH::C, GW = SH::GW, LSP = SH::LSP;
+  constexpr int NT = 64 * GW;
   const int solve = blockIdx.z;
-  SolveCtl* ctl = a.ctl + solve;
-  if (!a.ignore_done && ctl->done) return;
+  if (!a.ignore_done && a.ctl[solve].done) return;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x;
-  if (a.fin && blockIdx.x == 0) finalize_solve(a.f, solve, tid, kSmNT);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (a.fin && blockIdx.x == 0) finalize_solve(a.f, solve, tid, NT);
   const int x0 = blockIdx.x * C;
   const int nlc = min(C, a.n[0] - x0);
   const long long M = a.M;
   cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + (long long)solve * 2 * M + x0;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const long long stride = a.stride;
-  for (int i = tid; i < N * W; i += kSmNT) {
-    const int k = i / W;
-    const int r = i - k * W;
+  // line w = comp * C + column; its slot at lds + w * LSP
+#pragma unroll 4
+  for (int i = tid; i < N * GW; i += NT) {
+    const int k = i / GW;
+    const int r = i - k * GW;
     const int c = r / C;
     const int l = r - c * C;
-    lds[i] = l < nlc ? X[c * M + (long long)k * stride + l] : mk<T>(0, 0);
+    lds[r * LSP + k] = l < nlc ? X[c * M + (long long)k * stride + l] : mk<T>(0, 0);
   }
   __syncthreads();
-  sm_fft<T, N, W, true>(lds, tw, (T)-1, tid);
+  cx<T>* slot = lds + w * LSP;
+  cx<T> v0[B0][R0];
+#pragma unroll
+  for (int u = 0; u < B0; ++u) {
+    const int j = lane + 64 * u;
+    if (NB0 % 64 == 0 || j < NB0) {
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
+    }
+  }
+  sm_fft<T, N>(v0, slot, tw, (T)-1, lane);
+  __syncthreads();
   const SolveCoef& cf = a.coef[solve];
   const T ga = (T)cf.ga, gb = (T)cf.gb, keep = (T)cf.kz_keep;
-  for (int i = tid; i < N * C; i += kSmNT) {
+  for (int i = tid; i < N * C; i += NT) {
     const int k = i / C;
     const int l = i - k * C;
     if (l >= nlc) continue;
     const int m[3] = {x0 + l, k, 0};
     T tv[2][2];
     symbol_entries<T, 2>(a, m, tv);
-    cx<T> w[2] = {lds[k * W + l], lds[k * W + C + l]};
-    gamma_mode<T, 2>(a, cf, ga, gb, keep, m, tv, w);
-    lds[k * W + l] = w[0];
-    lds[k * W + C + l] = w[1];
+    cx<T> wv[2] = {lds[l * LSP + k], lds[(C + l) * LSP + k]};
+    gamma_mode<T, 2>(a, cf, ga, gb, keep, m, tv, wv);
+    lds[l * LSP + k] = wv[0];
+    lds[(C + l) * LSP + k] = wv[1];
   }
   __syncthreads();
-  sm_fft<T, N, W, true>(lds, tw, (T)1, tid);
-  for (int i = tid; i < N * W; i += kSmNT) {
-    const int k = i / W;
-    const int r = i - k * W;
+#pragma unroll
+  for (int u = 0; u < B0; ++u) {
+    const int j = lane + 64 * u;
+    if (NB0 % 64 == 0 || j < NB0) {
+#pragma unroll
+      for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
+    }
+  }
+  sm_fft<T, N>(v0, slot, tw, (T)1, lane);
+  __syncthreads();
+#pragma unroll 4
+  for (int i = tid; i < N * GW; i += NT) {
+    const int k = i / GW;
+    const int r = i - k * GW;
     const int c = r / C;
     const int l = r - c * C;
-    if (l < nlc) X[c * M + (long long)k * stride + l] = lds[i];
+    if (l < nlc) X[c * M + (long long)k * stride + l] = lds[r * LSP + k];
   }
 }
 

@@ -96,13 +96,26 @@ void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
     default: break;                  \
   }
 
-// Compile-time mixed-radix passes: false (nothing launched) for a length
-// without an instantiation.  x pass grid = (row blocks of smooth_lines rows,
-// d, solves); Gamma grid = (column tiles of smooth_cols columns, 1, solves).
+// Compile-time mixed-radix passes (one wave per line): false (nothing
+// launched) for a length without an instantiation.  x pass grid = (row
+// blocks of smooth_lines rows, d, solves); Gamma grid = (column tiles of
+// smooth_cols columns, 1, solves).
+// mk: the x pass's local map (MapKind).
+template <typename T, int K>
+bool launch_smooth_unit(const XArgs* xa, const GArgs* ga, dim3 grid, hipStream_t st, int n);
 template <typename T>
-bool launch_xpass_smooth(const XArgs& a, dim3 grid, hipStream_t st, int n);
+bool launch_xpass_smooth(const XArgs& a, dim3 grid, hipStream_t st, int n, int mk) {
+  switch (mk) {
+    case MAP_LIN: return launch_smooth_unit<T, MAP_LIN>(&a, nullptr, grid, st, n);
+    case MAP_LIN_DENS: return launch_smooth_unit<T, MAP_LIN_DENS>(&a, nullptr, grid, st, n);
+    case MAP_ACC_EM: return launch_smooth_unit<T, MAP_ACC_EM>(&a, nullptr, grid, st, n);
+    default: return launch_smooth_unit<T, MAP_ACC_MS>(&a, nullptr, grid, st, n);
+  }
+}
 template <typename T>
-bool launch_gamma_smooth(const GArgs& a, dim3 grid, hipStream_t st, int n);
+bool launch_gamma_smooth(const GArgs& a, dim3 grid, hipStream_t st, int n) {
+  return launch_smooth_unit<T, 4>(nullptr, &a, grid, st, n);
+}
 // Rows per x-pass workgroup and columns per Gamma tile (0: no instantiation).
 int smooth_lines(int n, int esz);
 int smooth_cols(int n, int esz);

@@ -74,11 +74,11 @@ int line_tile_max(int n, int esz, int D, int gr) {
 
 int smooth_lines(int n, int esz) {
   if (esz == 8) {
-#define C_(N) return sm_lines<float, N>()
+#define C_(N) return SmShape<float, N>::XW
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   } else {
-#define C_(N) return sm_lines<double, N>()
+#define C_(N) return SmShape<double, N>::XW
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   }
@@ -87,11 +87,11 @@ int smooth_lines(int n, int esz) {
 
 int smooth_cols(int n, int esz) {
   if (esz == 8) {
-#define C_(N) return sm_cols<float, N>()
+#define C_(N) return SmShape<float, N>::C
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   } else {
-#define C_(N) return sm_cols<double, N>()
+#define C_(N) return SmShape<double, N>::C
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   }

@@ -1,42 +1,40 @@
 // Instantiations of the compile-time mixed-radix passes for one precision
-// (SCFFT_T, set by the build).
+// (SCFFT_T) and one kernel family (SCFFT_SMK: 0..3 the x pass with that
+// local map, 4 the Gamma pass), both set by the build.
 #include "launch.hpp"
 
-#if !defined(SCFFT_T)
-#error "SCFFT_T (float or double) must be defined"
+#if !defined(SCFFT_T) || !defined(SCFFT_SMK)
+#error "SCFFT_T (float or double) and SCFFT_SMK (0..4) must be defined"
 #endif
 
 namespace scfft {
 namespace {
 
 template <typename T, int N>
-bool xpass_sm(const XArgs& a, dim3 grid, hipStream_t st) {
-  constexpr size_t lds = (size_t)sm_lines<T, N>() * N * sizeof(cx<T>);
-  static_assert(lds >= 5 * (kSmNT / 64) * sizeof(double), "reduction must fit the LDS");
-  hipLaunchKernelGGL((xpass_sm_kernel<T, N>), grid, dim3(kSmNT), lds, st, a);
-  return true;
-}
-
-template <typename T, int N>
-bool gamma_sm(const GArgs& a, dim3 grid, hipStream_t st) {
-  constexpr size_t lds = (size_t)2 * sm_cols<T, N>() * N * sizeof(cx<T>);
-  hipLaunchKernelGGL((gamma_sm_kernel<T, N>), grid, dim3(kSmNT), lds, st, a);
+bool smooth_sm(const XArgs& xa, const GArgs& ga, dim3 grid, hipStream_t st) {
+  using SH = SmShape<T, N>;
+  static_assert(SH::XLDS <= 65536 && SH::GLDS <= 65536, "one workgroup's LDS stays within 64 KiB");
+  if constexpr (SCFFT_SMK == 4) {
+    (void)xa;
+    hipLaunchKernelGGL((gamma_sm_kernel<T, N>), grid, dim3(64 * SH::GW), (size_t)SH::GLDS, st, ga);
+  } else {
+    (void)ga;
+    hipLaunchKernelGGL((xpass_sm_kernel<T, N, SCFFT_SMK>), grid, dim3(64 * SH::XW),
+                       (size_t)SH::XLDS, st, xa);
+  }
   return true;
 }
 
 }  // namespace
 
 template <>
-bool launch_xpass_smooth<SCFFT_T>(const XArgs& a, dim3 grid, hipStream_t st, int n) {
-#define C_(N) return xpass_sm<SCFFT_T, N>(a, grid, st)
-  SCFFT_SMOOTH_SWITCH(n, C_)
-#undef C_
-  return false;
-}
-
-template <>
-bool launch_gamma_smooth<SCFFT_T>(const GArgs& a, dim3 grid, hipStream_t st, int n) {
-#define C_(N) return gamma_sm<SCFFT_T, N>(a, grid, st)
+bool launch_smooth_unit<SCFFT_T, SCFFT_SMK>(const XArgs* xa, const GArgs* ga, dim3 grid,
+                                            hipStream_t st, int n) {
+  static const XArgs x0{};
+  static const GArgs g0{};
+  const XArgs& x = xa ? *xa : x0;
+  const GArgs& g = ga ? *ga : g0;
+#define C_(N) return smooth_sm<SCFFT_T, N>(x, g, grid, st)
   SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   return false;

@@ -869,7 +869,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     } else if (p->p2x) {
       launch_xpass_reg<T>(a, grid, st, p->n[0], p->mk, p->kn.xr);
     } else if (p->smx) {
-      if (!launch_xpass_smooth<T>(a, grid, st, p->n[0])) return SCFFT_ERR_DEVICE;
+      if (!launch_xpass_smooth<T>(a, grid, st, p->n[0], p->mk)) return SCFFT_ERR_DEVICE;
     } else {
       const size_t lds =
           std::max((size_t)p->xL * p->n[0] * esz, (size_t)5 * (kNT / 64) * sizeof(double));
@@ -1130,7 +1130,8 @@ scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const 
   // Several plans (a batch of structures) become parallel branches of the
   // graph, at most kBranches, each a chain of its plans' iterations; plans
   // go to the least loaded branch, largest first (cost: voxels x solves).
-  const int nb = (int)std::min<size_t>(plans.size(), kBranches);
+  const int nbmax = std::max(1, std::min(kBranches, env_int("SCFFT_BRANCHES", kBranches)));
+  const int nb = (int)std::min<size_t>(plans.size(), (size_t)nbmax);
   std::vector<int> branch(plans.size(), 0);
   if (nb > 1) {
     std::vector<size_t> order(plans.size());

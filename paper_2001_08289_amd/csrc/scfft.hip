@@ -1192,7 +1192,8 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
                       const std::vector<const double*>& dens, int max_iter, int check_every,
                       hipStream_t st, double* elapsed_ms, bool allow_graph = true,
                       hipEvent_t* timing = nullptr) {
-  const int ce = std::max(1, check_every);
+  // a solve shorter than one check interval runs as a single chunk
+  const int ce = std::max(1, std::min(check_every, max_iter + 1));
   const bool use_graph = allow_graph && !std::getenv("SCFFT_NO_GRAPH");
   hipStream_t ws = st;
   if (use_graph) {

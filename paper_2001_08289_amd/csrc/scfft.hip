@@ -199,8 +199,13 @@ scfft_status check_dims(int d, const int* n, int prec) {
   return SCFFT_OK;
 }
 
-scfft_status ensure_hist(Plan* p, int cap) {
-  if (cap <= p->hist_cap) return SCFFT_OK;
+scfft_status ensure_hist(Plan* p, int need) {
+  if (need <= p->hist_cap) return SCFFT_OK;
+  if (need > (1 << 27)) return SCFFT_ERR_OOM;
+  // room for at least 1024 iterates, in powers of two: solves of other
+  // lengths then reuse the buffers, and with them the captured graphs
+  int cap = 1024;
+  while (cap < need) cap *= 2;
   if (p->hist_r) (void)hipFree(p->hist_r);
   if (p->hist_s) (void)hipFree(p->hist_s);
   p->hist_r = nullptr;
@@ -1067,7 +1072,38 @@ void free_graphs() {
   g_graphs.clear();
 }
 
+// Drops the oldest cached graphs beyond `keep`.  Called only before a loop
+// gathers its graphs, so no handle a running loop holds is destroyed.
+void trim_graphs(size_t keep) {
+  while (g_graphs.size() > keep) {
+    (void)hipGraphExecDestroy(g_graphs.front().exec);
+    g_graphs.erase(g_graphs.begin());
+  }
+}
+
 // Graph capture needs a stream other than the legacy default stream.
+// Per device: the loop's two timing events and the event that orders the
+// work stream after the caller's stream (created once).
+struct LoopEvents {
+  hipEvent_t t0, t1, dep;
+};
+std::map<int, LoopEvents> g_loop_events;
+
+scfft_status loop_events(LoopEvents* out) {
+  int dev = 0;
+  SCFFT_HIP(hipGetDevice(&dev));
+  auto it = g_loop_events.find(dev);
+  if (it == g_loop_events.end()) {
+    LoopEvents e{};
+    SCFFT_HIP(hipEventCreate(&e.t0));
+    SCFFT_HIP(hipEventCreate(&e.t1));
+    SCFFT_HIP(hipEventCreateWithFlags(&e.dep, hipEventDisableTiming));
+    it = g_loop_events.emplace(dev, e).first;
+  }
+  *out = it->second;
+  return SCFFT_OK;
+}
+
 scfft_status work_stream(hipStream_t st, hipStream_t* ws) {
   if (st != nullptr) {
     *ws = st;
@@ -1176,9 +1212,11 @@ scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const 
   const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e2 != hipSuccess) return SCFFT_ERR_DEVICE;
-  if (g_graphs.size() >= 32) {
-    (void)hipGraphExecDestroy(g_graphs.front().exec);
-    g_graphs.erase(g_graphs.begin());
+  // upload now, so that the first replay (perhaps inside a caller's timed
+  // region) does not pay for it
+  if (hipGraphUpload(exec, ws) != hipSuccess) {
+    (void)hipGraphExecDestroy(exec);
+    return SCFFT_ERR_DEVICE;
   }
   g_graphs.push_back(GraphEntry{key, exec});
   *out = exec;
@@ -1195,31 +1233,40 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
   // a solve shorter than one check interval runs as a single chunk
   const int ce = std::max(1, std::min(check_every, max_iter + 1));
   const bool use_graph = allow_graph && !std::getenv("SCFFT_NO_GRAPH");
+  LoopEvents lev;
+  {
+    scfft_status rc = loop_events(&lev);
+    if (rc != SCFFT_OK) return rc;
+  }
   hipStream_t ws = st;
   if (use_graph) {
     scfft_status rc = work_stream(st, &ws);
     if (rc != SCFFT_OK) return rc;
-    if (ws != st) SCFFT_HIP(hipStreamSynchronize(st));
+    if (ws != st) {
+      // the caller's set-up work on st comes first
+      SCFFT_HIP(hipEventRecord(lev.dep, st));
+      SCFFT_HIP(hipStreamWaitEvent(ws, lev.dep, 0));
+    }
   }
-  // A chunk of ce iterations is one graph; where fewer than ce iterations
-  // remain before max_iter, single-iteration graphs are replayed instead, so
-  // no launch beyond the last possible iterate is queued.
-  hipGraphExec_t exec = nullptr, exec1 = nullptr;
+  // A chunk of k iterations (k = ce, or what is left before max_iter, so no
+  // launch beyond the last possible iterate is queued) replays graphs of 2^b
+  // iterations: the largest (at most 64) as often as it fits, then one per
+  // remaining set bit of k.  The graphs of every power of two up to
+  // min(check_every, 64) are built at once on first use, so later solves of
+  // any length build none.
+  std::vector<hipGraphExec_t> pw;
   if (use_graph) {
-    scfft_status rc = get_graph(plans, phases, dens, 1, ws, &exec1);
-    if (rc == SCFFT_OK && ce > 1 && max_iter + 1 >= ce)
-      rc = get_graph(plans, phases, dens, ce, ws, &exec);
-    if (rc != SCFFT_OK) return rc;
+    trim_graphs(192);
+    for (int b = 0; (1 << b) <= std::min(std::max(1, check_every), 64); ++b) {
+      hipGraphExec_t g = nullptr;
+      scfft_status rc = get_graph(plans, phases, dens, 1 << b, ws, &g);
+      if (rc != SCFFT_OK) return rc;
+      pw.push_back(g);
+    }
   }
-  // timing events: the caller's (created once) or made here
-  hipEvent_t e0, e1;
-  if (timing) {
-    e0 = timing[0];
-    e1 = timing[1];
-  } else {
-    SCFFT_HIP(hipEventCreate(&e0));
-    SCFFT_HIP(hipEventCreate(&e1));
-  }
+  // timing events: the caller's or the loop's own
+  const hipEvent_t e0 = timing ? timing[0] : lev.t0;
+  const hipEvent_t e1 = timing ? timing[1] : lev.t1;
   SCFFT_HIP(hipEventRecord(e0, ws));
   // iterate n = 0..max_iter takes max_iter + 1 launches; a few spare chunks
   // cover solves whose stop flag is set by the last of them
@@ -1232,11 +1279,11 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
     const long long left = needed - launched;
     const int k = (int)(left >= ce || left <= 0 ? ce : left);
     if (use_graph) {
-      if (k == ce && exec) {
-        SCFFT_HIP(hipGraphLaunch(exec, ws));
-      } else {
-        for (int q = 0; q < k; ++q) SCFFT_HIP(hipGraphLaunch(exec1, ws));
-      }
+      const int top = (int)pw.size() - 1;
+      int rem = k;
+      for (; rem >= (1 << top); rem -= 1 << top) SCFFT_HIP(hipGraphLaunch(pw[top], ws));
+      for (int b = top - 1; b >= 0; --b)
+        if (rem & (1 << b)) SCFFT_HIP(hipGraphLaunch(pw[b], ws));
     } else {
       for (int q = 0; q < k; ++q)
         for (size_t i = 0; i < plans.size(); ++i) {
@@ -1264,10 +1311,6 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
   float ms = 0;
   SCFFT_HIP(hipEventElapsedTime(&ms, e0, e1));
   if (elapsed_ms) *elapsed_ms = ms;
-  if (!timing) {
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-  }
   if (!all_done) return SCFFT_ERR_DEVICE;   // the device never set its stop flag
   return SCFFT_OK;
 }

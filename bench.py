@@ -35,6 +35,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILE_SUMMARY = "xpass_gamma_2048sq_acc_em_fp32.txt"
 KERNEL_NAMES = {"xpass": "void scfft::xpass_r2c_kernel<float, 2048,",
                 "gamma": "void scfft::line_p2_kernel<float, 2048,"}
+PROFILE_SUMMARY_FP64 = "xpass_gamma_2048sq_acc_em_fp64.txt"
+KERNEL_NAMES_FP64 = {"xpass": "void scfft::xpass_r2c_kernel<double, 2048,",
+                     "gamma": "void scfft::line_p2_kernel<double, 2048,"}
 
 
 def algorithmic_bytes(scheme: str, precision: str, d: int, frac1: float, n0: int,
@@ -417,6 +420,20 @@ def main() -> int:
     plan_report["rules_pass_ms"] = {k: round(rule[k], 5) for k in ("xpass", "gamma")}
     del os.environ["SCFFT_TUNE"]
     scfft.release()
+    # the same iteration in fp64 (the time-to-tolerance reference): both
+    # kernels against the HBM roof, traffic from the committed fp64 summary
+    prof64 = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision="fp64",
+                                  alpha=0.25, beta=4.0, iters=args.profile_iters)
+    ab64 = algorithmic_bytes(hs["scheme"], "fp64", 2, frac1, N, real=True)
+    roofline_fp64 = {}
+    for k in ("xpass", "gamma"):
+        gbs = ab64[k] * N * N / (prof64[k] * 1e-3) / 1e9
+        roofline_fp64[k] = {
+            "ms": round(prof64[k], 5), "bytes_per_launch": ab64[k] * N * N,
+            "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(os.path.join(HERE, "profiles", PROFILE_SUMMARY_FP64),
+                                    KERNEL_NAMES_FP64[k])}
+    scfft.release()
 
     # ---------------------------------------------------------- sweep
     sweep = []
@@ -526,6 +543,7 @@ def main() -> int:
                    "grid": [N, N], "sweep_sigma1": list(SIGMAS), "schemes": list(SCHEMES),
                    "symbol": "rotated"},
         "roofline": roofline,
+        "roofline_fp64": roofline_fp64,
         "cpu_baseline": cpu,
         "speedup_time_to_tol": accel,
         "fp32_at_fp64_iterations": same_iters,

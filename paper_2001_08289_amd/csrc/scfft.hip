@@ -1229,7 +1229,8 @@ scfft_status get_graph(const std::vector<Plan*>& plans, const std::vector<const 
 scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const uint8_t*>& phases,
                       const std::vector<const double*>& dens, int max_iter, int check_every,
                       hipStream_t st, double* elapsed_ms, bool allow_graph = true,
-                      hipEvent_t* timing = nullptr) {
+                      hipEvent_t* timing = nullptr,
+                      std::vector<std::vector<SolveCtl>>* final_ctl = nullptr) {
   // a solve shorter than one check interval runs as a single chunk
   const int ce = std::max(1, std::min(check_every, max_iter + 1));
   const bool use_graph = allow_graph && !std::getenv("SCFFT_NO_GRAPH");
@@ -1312,17 +1313,25 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
   SCFFT_HIP(hipEventElapsedTime(&ms, e0, e1));
   if (elapsed_ms) *elapsed_ms = ms;
   if (!all_done) return SCFFT_ERR_DEVICE;   // the device never set its stop flag
+  // the last check read every solve's final control block
+  if (final_ctl) *final_ctl = std::move(host);
   return SCFFT_OK;
 }
 
+// `known`: the solve's final control block if the caller already has it
+// (from the loop's last check); then a result without fields or histories
+// needs no device access.
 scfft_status read_result(Plan* p, int solve, const scfft_problem* prob, scfft_result* res,
-                         hipStream_t st, double elapsed) {
+                         hipStream_t st, double elapsed, const SolveCtl* known = nullptr) {
   SolveCtl c;
-  SCFFT_HIP(hipMemcpyAsync(&c, p->ctl + solve, sizeof(SolveCtl), hipMemcpyDeviceToHost, st));
+  const bool hist = res->history_cap > 0 && (res->residual_history || res->sigma_history);
+  const bool device = !known || res->E || res->J || hist;
+  if (known) c = *known;
+  else SCFFT_HIP(hipMemcpyAsync(&c, p->ctl + solve, sizeof(SolveCtl), hipMemcpyDeviceToHost, st));
   scfft_status rc = launch_extract(p, solve, prob->phase, prob->density, res->E, res->J, st);
   if (rc != SCFFT_OK) return rc;
   const int n = c.iter;
-  if (res->history_cap > 0 && (res->residual_history || res->sigma_history)) {
+  if (hist) {
     const int cnt = std::min(std::min(res->history_cap, n + 1), p->hist_cap);
     if (res->residual_history)
       SCFFT_HIP(hipMemcpyAsync(res->residual_history, p->hist_r + (size_t)solve * p->hist_cap,
@@ -1331,7 +1340,7 @@ scfft_status read_result(Plan* p, int solve, const scfft_problem* prob, scfft_re
       SCFFT_HIP(hipMemcpyAsync(res->sigma_history, p->hist_s + (size_t)solve * p->hist_cap * 2,
                                2 * sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
   }
-  SCFFT_HIP(hipStreamSynchronize(st));
+  if (device) SCFFT_HIP(hipStreamSynchronize(st));
   res->sigma_star.re = c.sstar_re;
   res->sigma_star.im = c.sstar_im;
   for (int i = 0; i < 3; ++i) {
@@ -1510,9 +1519,11 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   rc = launch_init(p, st);
   if (rc != SCFFT_OK) return rc;
   double ms = 0;
-  rc = run_loop({p}, {prob->phase}, {prob->density}, opt->max_iter, opt->check_every, st, &ms);
+  std::vector<std::vector<SolveCtl>> fin;
+  rc = run_loop({p}, {prob->phase}, {prob->density}, opt->max_iter, opt->check_every, st, &ms,
+                true, nullptr, &fin);
   if (rc != SCFFT_OK) return rc;
-  return read_result(p, 0, prob, res, st, ms);
+  return read_result(p, 0, prob, res, st, ms, &fin[0][0]);
 }
 
 scfft_status scfft_plan_info(const scfft_problem* prob, const scfft_options* opt, int* info,
@@ -1776,13 +1787,15 @@ scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scff
     de[i] = probs[i].density;
   }
   double ms = 0;
-  scfft_status rc = run_loop(plans, ph, de, o0.max_iter, o0.check_every, st, &ms);
+  std::vector<std::vector<SolveCtl>> fin;
+  scfft_status rc = run_loop(plans, ph, de, o0.max_iter, o0.check_every, st, &ms, true, nullptr,
+                             &fin);
   if (rc != SCFFT_OK) return rc;
   scfft_status worst = SCFFT_OK;
   for (int i = 0; i < nprob; ++i)
     for (int j = 0; j < nsig; ++j) {
       scfft_result* r = &results[(size_t)i * nsig + j];
-      scfft_status s = read_result(plans[i], j, &probs[i], r, st, ms);
+      scfft_status s = read_result(plans[i], j, &probs[i], r, st, ms, &fin[i][j]);
       if (s == SCFFT_ERR_DEVICE || s == SCFFT_ERR_OOM) return s;
       if (s < worst) worst = s;
     }

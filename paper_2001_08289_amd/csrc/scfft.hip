@@ -1234,8 +1234,10 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
   // a solve shorter than one check interval runs as a single chunk
   const int ce = std::max(1, std::min(check_every, max_iter + 1));
   const bool use_graph = allow_graph && !std::getenv("SCFFT_NO_GRAPH");
-  LoopEvents lev;
-  {
+  // the loop's own events, when it needs any (a caller that brings its
+  // timing events and runs without graphs creates none)
+  LoopEvents lev{};
+  if (!timing || use_graph) {
     scfft_status rc = loop_events(&lev);
     if (rc != SCFFT_OK) return rc;
   }

@@ -294,7 +294,8 @@ def main() -> int:
                     help="only run the headline iteration with per-kernel timing (for rocprofv3)")
     ap.add_argument("--profile-workload", default="headline",
                     choices=["headline", "cube256_acc_em_fp32", "square2048_acc_em_fp64",
-                             "batch_fp32", "batch_fp64"],
+                             "batch_fp32", "batch_fp64", "gradient1024_fp32",
+                             "gradient1024_fp64"],
                     help="workload of --profile-only")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 3D cube, batched-sweep and gradient workloads")
@@ -341,6 +342,17 @@ def main() -> int:
             torch.cuda.synchronize()
             print(json.dumps({"workload": args.profile_workload, "iterations": args.profile_iters,
                               "grids": list(inputs.BATCH_GRIDS)}), flush=True)
+            return 0
+        if args.profile_workload.startswith("gradient"):
+            # the graded 1024^2 medium: forward EM solve, transposed adjoint
+            # solve and the gradient kernel, a fixed number of iterations each
+            prec = args.profile_workload.split("_")[1]
+            rho = torch.as_tensor(inputs.density_field(1024, seed=5)).cuda()
+            scfft.gradient(density=rho, sigma1=20.0, e0=(1.0, 0.0), precision=prec, tol=-1.0,
+                           max_iter=args.profile_iters, stag_window=0, div_factor=0.0)
+            torch.cuda.synchronize()
+            print(json.dumps({"workload": args.profile_workload,
+                              "iterations": args.profile_iters}), flush=True)
             return 0
         if args.profile_workload == "cube256_acc_em_fp32":
             # 256^3 cube array, sigma1 = 100, the symmetrised power-iteration interval

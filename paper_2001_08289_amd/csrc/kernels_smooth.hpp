@@ -72,9 +72,11 @@ struct SmShape {
   static constexpr int R0 = sm_radix(N, 0);          // radix of the first pass
   static constexpr int B0 = (N / R0 + 63) / 64;      // its butterflies per lane
   // x pass: rows (waves) per workgroup; Gamma pass: columns per tile, one
-  // wave per column and component
-  static constexpr int XW = 4;
-  static constexpr int C = sizeof(T) == 4 ? 4 : 2;
+  // wave per column and component (measured on the 16-grid batch: 2 rows
+  // and 8 fp32 columns (64-byte row pieces, up to 120 KiB of LDS) beat
+  // 4 rows and 4 columns by 8 %; fp64 keeps 2 columns)
+  static constexpr int XW = 2;
+  static constexpr int C = sizeof(T) == 4 ? 8 : 2;
   static constexpr int GW = 2 * C;
   static constexpr int XLDS = XW * LSP * (int)sizeof(cx<T>) + 5 * XW * 8;
   static constexpr int GLDS = GW * LSP * (int)sizeof(cx<T>);

@@ -13,9 +13,18 @@ namespace {
 template <typename T, int N>
 bool smooth_sm(const XArgs& xa, const GArgs& ga, dim3 grid, hipStream_t st) {
   using SH = SmShape<T, N>;
-  static_assert(SH::XLDS <= 65536 && SH::GLDS <= 65536, "one workgroup's LDS stays within 64 KiB");
+  static_assert(SH::XLDS <= 65536 && SH::GLDS <= 160 * 1024, "workgroup LDS within gfx950's");
   if constexpr (SCFFT_SMK == 4) {
     (void)xa;
+    if (SH::GLDS > 65536) {
+      // LDS beyond 64 KiB per workgroup (gfx950 has 160 KiB per CU) is opt-in
+      static bool set = false;
+      if (!set) {
+        (void)hipFuncSetAttribute((const void*)gamma_sm_kernel<T, N>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)SH::GLDS);
+        set = true;
+      }
+    }
     hipLaunchKernelGGL((gamma_sm_kernel<T, N>), grid, dim3(64 * SH::GW), (size_t)SH::GLDS, st, ga);
   } else {
     (void)ga;

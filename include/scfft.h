@@ -151,7 +151,14 @@ typedef struct {
   double elapsed_ms;      /* device time of the iteration loop (HIP events) */
 } scfft_result;
 
-/* Solve one problem (eqs. J12-J13) with one scheme. */
+/* Solve one problem (eqs. J12-J13) with one scheme.  A solve with
+ * max_iter = m runs m + 1 passes (iterates 0..m).  The passes run as
+ * replays of HIP graphs of 2^b iterations (b up to log2 min(check_every,
+ * 64)), captured on opt->stream (on an internal non-blocking stream when it
+ * is NULL, ordered after the caller's earlier work) and built, with the
+ * plan, on the first solve of a configuration; SCFFT_NO_GRAPH launches the
+ * same kernels one by one.  Plans, graphs and workspaces are cached until
+ * scfft_release. */
 scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt,
                          scfft_result* res);
 

@@ -88,3 +88,20 @@ def test_smooth_batch_of_mixed_grids(env):
                               max_iter=400, fields=False)
             got = res[i * 2 + j]["sigma_star"]
             assert abs(got - one["sigma_star"]) / abs(one["sigma_star"]) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(12, 10, 48), (6, 8, 90)])
+@pytest.mark.parametrize("scheme,s1", [("acc_em", 3 + 2j), ("ms", 10.0)])
+def test_smooth_x_pass_in_3d(shape, scheme, s1, env):
+    # 3D full-complex fields: the x pass takes the compile-time passes, the
+    # strided y and z passes the runtime-planned ones
+    chi = inputs.random_phase(shape, 0.3, seed=24)
+    ref = osolver.solve(chi, s1, [1.0, 0.0, 0.0], scheme, alpha=0.25, beta=4.0, tol=-1,
+                        max_iter=3, stag_window=0, div_factor=0)
+    info = scfft.plan_info(chi, s1, (1, 0, 0), scheme, precision="fp64")
+    assert info["x_engine"] == SMOOTH and info["gamma_engine"] == 0, info
+    for precision, bound in (("fp64", 1e-11), ("fp32", 2e-6)):
+        got = scfft.solve(chi, s1, (1, 0, 0), scheme, precision=precision, tol=-1, max_iter=3,
+                          stag_window=0, div_factor=0)
+        assert _rel(got["E"].cpu().numpy(), ref["E"]) < bound, (precision, shape)
+        assert abs(got["sigma_star"] - ref["sigma_star"]) / abs(ref["sigma_star"]) < bound

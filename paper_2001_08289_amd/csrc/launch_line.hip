@@ -45,8 +45,8 @@ void line_n(const GArgs& a, dim3 grid, hipStream_t st) {
 
 template <>
 void launch_line_reg<SCFFT_T, SCFFT_D>(const GArgs& a, dim3 grid, hipStream_t st, int n, int gr) {
-  // the 2D Gamma pass offers radix 4 and 8; the 3D passes radix 8
-  if (SCFFT_D == 2 && gr == 4) {
+  // the Gamma passes offer radix 4 and 8; the plain 3D y pass radix 8
+  if (SCFFT_D != 1 && gr == 4) {
 #define C_(N) line_n<SCFFT_T, N, SCFFT_D, 4>(a, grid, st)
     SCFFT_P2_SWITCH(n, C_)
 #undef C_

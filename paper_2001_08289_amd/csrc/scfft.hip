@@ -267,7 +267,7 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   if (p->p2g) {
     k.gr = env_int("SCFFT_GR", want.gr ? want.gr : rule_gr(nlast, esz, d));
     const bool r16ok = d == 2 && nlast == 2048 && esz == 16;
-    if (d != 2) k.gr = 8;
+    if (d == 3 && k.gr != 4) k.gr = 8;
     if (k.gr == 16 && !r16ok) k.gr = rule_gr(nlast, esz, d) == 16 ? 8 : rule_gr(nlast, esz, d);
     if (k.gr != 4 && k.gr != 8 && k.gr != 16) k.gr = rule_gr(nlast, esz, d);
     if (env_int("SCFFT_R16", 1) == 0 && k.gr == 16) k.gr = 8;
@@ -483,7 +483,7 @@ scfft_status autotune(int dev, int d, const int* n, int prec, bool st, int symbo
   std::vector<int> xrs = probe.p2x ? std::vector<int>{4, 8} : std::vector<int>{0};
   std::vector<std::pair<int, int>> gcs;   // (radix, tile width)
   if (probe.p2g) {
-    std::vector<int> radices = d == 2 ? std::vector<int>{4, 8} : std::vector<int>{8};
+    std::vector<int> radices{4, 8};
     if (d == 2 && nlast == 2048 && esz == 16) radices.push_back(16);
     for (int r : radices) {
       if (nlast < r) continue;
@@ -942,7 +942,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
       if constexpr (sizeof(T) == 8) launch_line_r16_f64_2048(q, grid, st);
     } else if (p->p2g) {
       if (d == 2) launch_line_reg<T, 2>(q, grid, st, nl, p->kn.gr);
-      else launch_line_reg<T, 3>(q, grid, st, nl, 8);
+      else launch_line_reg<T, 3>(q, grid, st, nl, p->kn.gr);
     } else if (p->smg) {
       if (!launch_gamma_smooth<T>(q, grid, st, nl)) return SCFFT_ERR_DEVICE;
     } else {

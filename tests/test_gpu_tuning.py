@@ -54,7 +54,7 @@ def test_every_forced_candidate_matches_oracle(case, clean_env):
     clean_env.setenv("SCFFT_TUNE", "0")
     combos = []
     for xr in ("4", "8"):
-        for gr in (("4", "8") if len(shape) == 2 else ("8",)):
+        for gr in ("4", "8"):
             for c in ("1", "2", "4", "8"):
                 combos.append({"SCFFT_XR": xr, "SCFFT_GR": gr, "SCFFT_LINE_C": c})
     if len(shape) == 3:
@@ -74,7 +74,7 @@ def test_every_forced_candidate_matches_oracle(case, clean_env):
         assert info["tuned"] == 0
         if "SCFFT_XR" in env:
             assert info["x_radix"] == int(env["SCFFT_XR"])
-        if "SCFFT_GR" in env and len(shape) == 2:
+        if "SCFFT_GR" in env:
             assert info["gamma_radix"] == int(env["SCFFT_GR"])
 
 

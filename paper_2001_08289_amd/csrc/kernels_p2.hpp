@@ -106,8 +106,8 @@ __global__ __launch_bounds__((XPassShape<N, R>::NTH)) void xpass_p2_kernel(XArgs
 // Lines per workgroup of the strided passes.  Every line keeps D LDS slots
 // (its D components are transformed together); the tile is the widest power
 // of two (at most 8 lines, 512 threads) whose slots fit the LDS budget,
-// preferring the padded slot layout -- measured optimum on MI355X: 2 columns
-// at 2048^2 (fp32), 8 lines at 256^3.
+// preferring the padded slot layout; narrower tiles (CW) are the autotuner's
+// other candidates.
 constexpr int kLineLdsBudget = 81920;
 
 template <typename T, int N, int R, int D, int CW = 0>

@@ -12,19 +12,6 @@
 
 namespace scfft {
 
-// Register FFT radix per pass (measured on MI355X, fp32 and fp64): radix 4
-// (twice the threads per line, more waves in flight) wins for the x pass up
-// to n0 = 1024 (fp64: 2048) and for the 2D Gamma pass up to 1024; radix 8
-// (fewer LDS exchanges) wins for longer lines and for the 3D strided passes.
-template <typename T, int N>
-constexpr int xpass_radix() {
-  return (N <= 1024 || (sizeof(T) == 8 && N <= 2048)) ? 4 : 8;
-}
-template <typename T, int N, int D>
-constexpr int line_radix() {
-  return (D == 2 && N <= 1024) ? 4 : 8;
-}
-
 #define SCFFT_P2_SWITCH(n, CALL)  \
   switch (n) {                    \
     case 16: CALL(16); break;     \
@@ -52,7 +39,7 @@ void launch_xpass_reg(const XArgs& a, dim3 grid, hipStream_t st, int n0, int mk,
 // Register-resident strided pass over lines of length n: D = 2 / 3 the Gamma
 // pass of a 2D / 3D grid (all components), D = 1 a plain 3D y pass; a.C is
 // the tile width (one of 1, 2, 4, 8; anything else the widest that fits);
-// gr the register radix (D = 2: 4 or 8; D = 1, 3: 8).
+// gr the register radix (D = 2, 3: 4 or 8; D = 1: 8).
 template <typename T, int D>
 void launch_line_reg(const GArgs& a, dim3 grid, hipStream_t st, int n, int gr);
 

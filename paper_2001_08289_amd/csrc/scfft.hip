@@ -155,6 +155,8 @@ struct Plan {
   Knobs kn;                                      // resolved speed choices
   bool tuned = false;                            // kn came from the autotuner
   int mk = MAP_LIN;                              // local map of the current solves
+  bool no_alloc = false;                         // workspace carved from the fixed array
+  SolveCtl* ctl_host = nullptr;                  // pinned: the loop's stop-flag reads
   bool real = false;                             // real-field mode (half spectra)
   bool packed = false;                           // 2D real mode: kx = 0 and n0/2 share column 0
   int H = 0;                                     // stored x-spectrum length
@@ -181,6 +183,7 @@ void free_plan(Plan* p) {
                   p->tw[0], p->tw[1], p->tw[2], p->sym[0], p->sym[1], p->sym[2]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  if (p->ctl_host) (void)hipHostFree(p->ctl_host);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -1296,12 +1299,20 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
     }
     launched += k;
     all_done = true;
+    // the loop's time ends with the last chunk's launches, before its read
+    SCFFT_HIP(hipEventRecord(e1, ws));
     for (size_t i = 0; i < plans.size(); ++i) {
-      host[i].resize(plans[i]->nsolve);
-      SCFFT_HIP(hipMemcpyAsync(host[i].data(), plans[i]->ctl, sizeof(SolveCtl) * plans[i]->nsolve,
-                               hipMemcpyDeviceToHost, ws));
+      Plan* q = plans[i];
+      host[i].resize(q->nsolve);
+      if (!q->no_alloc && !q->ctl_host)
+        SCFFT_HIP(hipHostMalloc((void**)&q->ctl_host, sizeof(SolveCtl) * q->nsolve));
+      SCFFT_HIP(hipMemcpyAsync(q->ctl_host ? (void*)q->ctl_host : (void*)host[i].data(), q->ctl,
+                               sizeof(SolveCtl) * q->nsolve, hipMemcpyDeviceToHost, ws));
     }
     SCFFT_HIP(hipStreamSynchronize(ws));
+    for (size_t i = 0; i < plans.size(); ++i)
+      if (plans[i]->ctl_host)
+        std::memcpy(host[i].data(), plans[i]->ctl_host, sizeof(SolveCtl) * plans[i]->nsolve);
     for (size_t i = 0; i < plans.size() && all_done; ++i)
       for (const auto& c : host[i])
         if (!c.done) {
@@ -1309,8 +1320,7 @@ scfft_status run_loop(const std::vector<Plan*>& plans, const std::vector<const u
           break;
         }
   }
-  SCFFT_HIP(hipEventRecord(e1, ws));
-  SCFFT_HIP(hipEventSynchronize(e1));
+  SCFFT_HIP(hipEventSynchronize(e1));   // complete already: the stream was synchronised
   float ms = 0;
   SCFFT_HIP(hipEventElapsedTime(&ms, e0, e1));
   if (elapsed_ms) *elapsed_ms = ms;
@@ -2377,6 +2387,7 @@ scfft_status scfft_solve_noalloc(const scfft_problem* prob, const scfft_options*
   rc = scratch_for_device(dev, &sd);
   if (rc != SCFFT_OK) return rc;
   Plan p;
+  p.no_alloc = true;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
   const bool real = real_ok(sp, prob->d, prob->n);
   // the knobs scfft_solve tuned for this configuration, if any (tuning itself

@@ -549,7 +549,9 @@ def main() -> int:
         "value": value, "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "passes_timed": res["iterations"] + 1,
         "device_loop_ms_per_step": device_ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 complex fields, fp64 reductions)",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "dtype_detail": "fp32 fields (real-space rows, complex half spectra), fp64 reductions and "
+                        "scheme scalars",
         "data": "synthetic",
         "config": {"workload": "2D periodic square array of squares at 25% (centred square of side "
                                "N/2), 2048x2048, e0 = e1; headline: accelerated scheme (EM in H'', "

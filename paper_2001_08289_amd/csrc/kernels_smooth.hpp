@@ -71,15 +71,25 @@ struct SmShape {
   static constexpr int LSP = (N + Q - 2) / Q * Q + 1;
   static constexpr int R0 = sm_radix(N, 0);          // radix of the first pass
   static constexpr int B0 = (N / R0 + 63) / 64;      // its butterflies per lane
-  // x pass: rows (waves) per workgroup; Gamma pass: columns per tile, one
-  // wave per column and component (measured on the 16-grid batch: 2 rows
-  // and 8 fp32 columns (64-byte row pieces, up to 120 KiB of LDS) beat
-  // 4 rows and 4 columns by 8 %; fp64 keeps 2 columns)
+  // x pass: rows (waves) per workgroup (measured on the 16-grid batch: two
+  // rows beat four)
   static constexpr int XW = 2;
-  static constexpr int C = sizeof(T) == 4 ? 8 : 2;
-  static constexpr int GW = 2 * C;
   static constexpr int XLDS = XW * LSP * (int)sizeof(cx<T>) + 5 * XW * 8;
-  static constexpr int GLDS = GW * LSP * (int)sizeof(cx<T>);
+};
+
+// Strided passes: tiles of C adjacent columns, one wave per column and
+// component (D components: 2 / 3 the Gamma pass of a 2D / 3D grid, 1 a plain
+// 3D y pass).  2D Gamma, measured on the 16-grid batch: 8 fp32 columns
+// (64-byte row pieces) beat 4 by 8 %; fp64 keeps 2.  The y pass takes
+// 64-byte pieces in both precisions; the 3D Gamma pass halves the 2D widths
+// to stay within 16 waves.
+template <typename T, int N, int D>
+struct SmTile {
+  static constexpr bool F = sizeof(T) == 4;
+  static constexpr int C = D == 1 ? (F ? 8 : 4) : D == 2 ? (F ? 8 : 2) : (F ? 4 : 2);
+  static constexpr int GW = D * C;
+  static constexpr int LDS = GW * SmShape<T, N>::LSP * (int)sizeof(cx<T>);
+  static_assert(GW <= 16, "at most 1024 threads per workgroup");
 };
 
 // One radix-r pass of a wave's line (slot: N points at slot[0..N)).  P = 0
@@ -228,28 +238,37 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
                              gridDim.x, tid);
 }
 
-// Gamma pass of a 2D full-complex field: a tile of C adjacent columns, one
-// wave per column and component.  The tile is staged through LDS in row
-// segments; each wave runs the forward y-FFT of its line; Gamma_1 of eq. J11
-// (J44-J45 in H'') with the scheme's k = 0 source couples the two components
-// of every mode; each wave runs the inverse y-FFT; the tile is stored back.
-// Workgroup 0 of each solve also reduces the x pass's partial sums and
-// applies the stop rules.
-template <typename T, int N>
-__global__ __launch_bounds__((64 * SmShape<T, N>::GW)) void gamma_sm_kernel(GArgs a) {
+// Strided pass of a full-complex field over lines of N points along the
+// last axis (a.mode 0: forward FFT, Gamma_1 of eq. J11 (J44-J45 in H'') with
+// the scheme's k = 0 source, inverse FFT, all D = d components) or along y in
+// 3D (mode 1 / 2: forward / inverse FFT of one component, D = 1).  A tile of
+// C adjacent columns, one wave per column and component: the tile is staged
+// through LDS in row pieces, each wave transforms its own line, the Gamma
+// step couples the components of every mode, and the tile is stored back.
+// Workgroup (0, 0) of each solve's Gamma pass also reduces the x pass's
+// partial sums and applies the stop rules.
+template <typename T, int N, int D>
+__global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GArgs a) {
   using SH = SmShape<T, N>;
-  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, C = SH::C, GW = SH::GW, LSP = SH::LSP;
-  constexpr int NT = 64 * GW;
-  const int solve = blockIdx.z;
+  using TS = SmTile<T, N, D>;
+  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, LSP = SH::LSP;
+  constexpr int C = TS::C, GW = TS::GW, NT = 64 * GW;
+  const bool gam = (a.mode == 0);
+  const int d = a.d;
+  const int solve = gam ? blockIdx.z : blockIdx.z / d;
+  const int comp0 = gam ? 0 : blockIdx.z % d;
   if (!a.ignore_done && a.ctl[solve].done) return;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (a.fin && blockIdx.x == 0) finalize_solve(a.f, solve, tid, NT);
+  if (a.fin && blockIdx.x == 0 && blockIdx.y == 0 && comp0 == 0)
+    finalize_solve(a.f, solve, tid, NT);
   const int x0 = blockIdx.x * C;
   const int nlc = min(C, a.n[0] - x0);
   const long long M = a.M;
-  cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + (long long)solve * 2 * M + x0;
+  // 2D Gamma: x0; 3D Gamma: x0 + y rp; 3D y pass: x0 + z rp n1
+  const long long off = x0 + (long long)blockIdx.y * a.rp * (gam ? 1 : a.n[1]);
+  cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M + off;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const long long stride = a.stride;
   // line w = comp * C + column; its slot at lds + w * LSP
@@ -264,40 +283,48 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::GW)) void gamma_sm_kernel(GArg
   __syncthreads();
   cx<T>* slot = lds + w * LSP;
   cx<T> v0[B0][R0];
+  if (a.mode != 2) {
 #pragma unroll
-  for (int u = 0; u < B0; ++u) {
-    const int j = lane + 64 * u;
-    if (NB0 % 64 == 0 || j < NB0) {
+    for (int u = 0; u < B0; ++u) {
+      const int j = lane + 64 * u;
+      if (NB0 % 64 == 0 || j < NB0) {
 #pragma unroll
-      for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
+        for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
+      }
     }
+    sm_fft<T, N>(v0, slot, tw, (T)-1, lane);
   }
-  sm_fft<T, N>(v0, slot, tw, (T)-1, lane);
-  __syncthreads();
-  const SolveCoef& cf = a.coef[solve];
-  const T ga = (T)cf.ga, gb = (T)cf.gb, keep = (T)cf.kz_keep;
-  for (int i = tid; i < N * C; i += NT) {
-    const int k = i / C;
-    const int l = i - k * C;
-    if (l >= nlc) continue;
-    const int m[3] = {x0 + l, k, 0};
-    T tv[2][2];
-    symbol_entries<T, 2>(a, m, tv);
-    cx<T> wv[2] = {lds[l * LSP + k], lds[(C + l) * LSP + k]};
-    gamma_mode<T, 2>(a, cf, ga, gb, keep, m, tv, wv);
-    lds[l * LSP + k] = wv[0];
-    lds[(C + l) * LSP + k] = wv[1];
-  }
-  __syncthreads();
+  if constexpr (D > 1) {
+    __syncthreads();
+    const SolveCoef& cf = a.coef[solve];
+    const T ga = (T)cf.ga, gb = (T)cf.gb, keep = (T)cf.kz_keep;
+    for (int i = tid; i < N * C; i += NT) {
+      const int k = i / C;
+      const int l = i - k * C;
+      if (l >= nlc) continue;
+      const int m[3] = {x0 + l, D == 2 ? k : (int)blockIdx.y, D == 2 ? 0 : k};
+      T tv[D][2];
+      symbol_entries<T, D>(a, m, tv);
+      cx<T> wv[D];
 #pragma unroll
-  for (int u = 0; u < B0; ++u) {
-    const int j = lane + 64 * u;
-    if (NB0 % 64 == 0 || j < NB0) {
+      for (int c = 0; c < D; ++c) wv[c] = lds[(c * C + l) * LSP + k];
+      gamma_mode<T, D>(a, cf, ga, gb, keep, m, tv, wv);
 #pragma unroll
-      for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
+      for (int c = 0; c < D; ++c) lds[(c * C + l) * LSP + k] = wv[c];
     }
+    __syncthreads();
   }
-  sm_fft<T, N>(v0, slot, tw, (T)1, lane);
+  if (a.mode != 1) {
+#pragma unroll
+    for (int u = 0; u < B0; ++u) {
+      const int j = lane + 64 * u;
+      if (NB0 % 64 == 0 || j < NB0) {
+#pragma unroll
+        for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
+      }
+    }
+    sm_fft<T, N>(v0, slot, tw, (T)1, lane);
+  }
   __syncthreads();
 #pragma unroll 4
   for (int i = tid; i < N * GW; i += NT) {

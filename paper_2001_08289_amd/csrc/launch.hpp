@@ -51,9 +51,9 @@ int line_tile_max(int n, int esz, int D, int gr);
 // fp64 Gamma pass of 2048-point columns with radix-16 register FFTs.
 void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
 
-// Line lengths with compile-time mixed-radix passes (2D full-complex x and
-// Gamma passes); every other 2/3/5-smooth length takes the runtime-planned
-// passes below.
+// Line lengths with compile-time mixed-radix passes (full-complex x pass,
+// Gamma pass, 3D y pass); every other 2/3/5-smooth length takes the
+// runtime-planned passes below.
 #define SCFFT_SMOOTH_SWITCH(n, CALL) \
   switch (n) {                       \
     case 48: CALL(48);               \
@@ -86,7 +86,8 @@ void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
 // Compile-time mixed-radix passes (one wave per line): false (nothing
 // launched) for a length without an instantiation.  x pass grid = (row
 // blocks of smooth_lines rows, d, solves); Gamma grid = (column tiles of
-// smooth_cols columns, 1, solves).
+// smooth_cols columns, 1 (2D) or n1 (3D), solves); 3D y pass grid = (column
+// tiles, n2, solves x 3).
 // mk: the x pass's local map (MapKind).
 template <typename T, int K>
 bool launch_smooth_unit(const XArgs* xa, const GArgs* ga, dim3 grid, hipStream_t st, int n);
@@ -100,12 +101,18 @@ bool launch_xpass_smooth(const XArgs& a, dim3 grid, hipStream_t st, int n, int m
   }
 }
 template <typename T>
-bool launch_gamma_smooth(const GArgs& a, dim3 grid, hipStream_t st, int n) {
-  return launch_smooth_unit<T, 4>(nullptr, &a, grid, st, n);
+bool launch_gamma_smooth(const GArgs& a, dim3 grid, hipStream_t st, int n, int d) {
+  return d == 2 ? launch_smooth_unit<T, 4>(nullptr, &a, grid, st, n)
+                : launch_smooth_unit<T, 5>(nullptr, &a, grid, st, n);
 }
-// Rows per x-pass workgroup and columns per Gamma tile (0: no instantiation).
+template <typename T>
+bool launch_ypass_smooth(const GArgs& a, dim3 grid, hipStream_t st, int n) {
+  return launch_smooth_unit<T, 6>(nullptr, &a, grid, st, n);
+}
+// Rows per x-pass workgroup; columns per strided tile for D components
+// (2 / 3: Gamma pass, 1: 3D y pass).  0: no instantiation.
 int smooth_lines(int n, int esz);
-int smooth_cols(int n, int esz);
+int smooth_cols(int n, int esz, int D);
 
 // LDS-staged mixed-radix passes (any 2/3/5-smooth length).
 template <typename T>

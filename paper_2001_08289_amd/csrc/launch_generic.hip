@@ -85,13 +85,13 @@ int smooth_lines(int n, int esz) {
   return 0;
 }
 
-int smooth_cols(int n, int esz) {
+int smooth_cols(int n, int esz, int D) {
   if (esz == 8) {
-#define C_(N) return SmShape<float, N>::C
+#define C_(N) return D == 2 ? SmTile<float, N, 2>::C : D == 3 ? SmTile<float, N, 3>::C : SmTile<float, N, 1>::C
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   } else {
-#define C_(N) return SmShape<double, N>::C
+#define C_(N) return D == 2 ? SmTile<double, N, 2>::C : D == 3 ? SmTile<double, N, 3>::C : SmTile<double, N, 1>::C
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   }

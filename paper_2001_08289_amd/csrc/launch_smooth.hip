@@ -1,10 +1,11 @@
 // Instantiations of the compile-time mixed-radix passes for one precision
 // (SCFFT_T) and one kernel family (SCFFT_SMK: 0..3 the x pass with that
-// local map, 4 the Gamma pass), both set by the build.
+// local map; 4 / 5 the Gamma pass of a 2D / 3D grid; 6 the 3D y pass), both
+// set by the build.
 #include "launch.hpp"
 
 #if !defined(SCFFT_T) || !defined(SCFFT_SMK)
-#error "SCFFT_T (float or double) and SCFFT_SMK (0..4) must be defined"
+#error "SCFFT_T (float or double) and SCFFT_SMK (0..6) must be defined"
 #endif
 
 namespace scfft {
@@ -13,19 +14,22 @@ namespace {
 template <typename T, int N>
 bool smooth_sm(const XArgs& xa, const GArgs& ga, dim3 grid, hipStream_t st) {
   using SH = SmShape<T, N>;
-  static_assert(SH::XLDS <= 65536 && SH::GLDS <= 160 * 1024, "workgroup LDS within gfx950's");
-  if constexpr (SCFFT_SMK == 4) {
+  static_assert(SH::XLDS <= 65536, "x-pass workgroup LDS within 64 KiB");
+  if constexpr (SCFFT_SMK >= 4) {
     (void)xa;
-    if (SH::GLDS > 65536) {
-      // LDS beyond 64 KiB per workgroup (gfx950 has 160 KiB per CU) is opt-in
+    constexpr int D = SCFFT_SMK == 4 ? 2 : SCFFT_SMK == 5 ? 3 : 1;
+    using TS = SmTile<T, N, D>;
+    static_assert(TS::LDS <= 160 * 1024, "workgroup LDS within gfx950's 160 KiB");
+    if (TS::LDS > 65536) {
+      // LDS beyond 64 KiB per workgroup is opt-in
       static bool set = false;
       if (!set) {
-        (void)hipFuncSetAttribute((const void*)gamma_sm_kernel<T, N>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)SH::GLDS);
+        (void)hipFuncSetAttribute((const void*)line_sm_kernel<T, N, D>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)TS::LDS);
         set = true;
       }
     }
-    hipLaunchKernelGGL((gamma_sm_kernel<T, N>), grid, dim3(64 * SH::GW), (size_t)SH::GLDS, st, ga);
+    hipLaunchKernelGGL((line_sm_kernel<T, N, D>), grid, dim3(64 * TS::GW), (size_t)TS::LDS, st, ga);
   } else {
     (void)ga;
     hipLaunchKernelGGL((xpass_sm_kernel<T, N, SCFFT_SMK>), grid, dim3(64 * SH::XW),

@@ -151,7 +151,7 @@ struct Plan {
   int xlines = 0, xL = 1, xblocks = 0;
   int gC = 1, yC = 1;
   bool p2x = false, p2g = false, p2y = false;   // register-resident passes
-  bool smx = false, smg = false;                 // compile-time mixed-radix passes
+  bool smx = false, smg = false, smy = false;    // compile-time mixed-radix passes
   Knobs kn;                                      // resolved speed choices
   bool tuned = false;                            // kn came from the autotuner
   int mk = MAP_LIN;                              // local map of the current solves
@@ -249,7 +249,8 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
   const bool sm_on = !std::getenv("SCFFT_NO_SMOOTH");
   p->smx = sm_on && !real && !p->p2x && smooth_lines(n[0], esz) > 0;
-  p->smg = sm_on && d == 2 && !p->p2g && smooth_cols(nlast, esz) > 0;
+  p->smg = sm_on && !p->p2g && smooth_cols(nlast, esz, d) > 0;
+  p->smy = sm_on && d == 3 && !p->p2y && smooth_cols(n[1], esz, 1) > 0;
   Knobs& k = p->kn;
   k = Knobs();
   // x pass radix
@@ -280,7 +281,7 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
     if (k.gr == 16) k.gC = cmax;   // one instantiation: the widest tile
   } else if (p->smg) {
     k.gr = 0;
-    k.gC = smooth_cols(nlast, esz);   // fixed by the instantiation
+    k.gC = smooth_cols(nlast, esz, d);   // fixed by the instantiation
   } else {
     k.gr = 0;
     const int cmax = std::min(pow2_floor(std::max(1, el / (nlast * d))), n[0]);
@@ -293,6 +294,8 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
     const int cmax = line_tile_max(n[1], esz, 1, 8);
     const int c = env_int("SCFFT_YC", env_int("SCFFT_LINE_C", want.yC ? want.yC : cmax));
     k.yC = (c == 1 || c == 2 || c == 4 || c == 8) ? std::min(c, cmax) : cmax;
+  } else if (d == 3 && p->smy) {
+    k.yC = smooth_cols(n[1], esz, 1);   // fixed by the instantiation
   } else if (d == 3) {
     const int cmax = std::min(pow2_floor(std::max(1, el / n[1])), n[0]);
     const int c = env_int("SCFFT_YC", env_int("SCFFT_LINE_C", want.yC ? want.yC : cmax));
@@ -510,7 +513,9 @@ scfft_status autotune(int dev, int d, const int* n, int prec, bool st, int symbo
     const int el = elems_for(prec);
     const int cmax = probe.p2y ? line_tile_max(n[1], esz, 1, 8)
                                : std::min(pow2_floor(std::max(1, el / n[1])), n[0]);
-    for (int c = 1; c <= std::min(cmax, 8); c *= 2) ycs.push_back(c);
+    if (probe.smy) ycs.push_back(probe.yC);
+    else
+      for (int c = 1; c <= std::min(cmax, 8); c *= 2) ycs.push_back(c);
   }
   const std::vector<int> packs = (real && d == 2 && probe.p2g) ? std::vector<int>{0, 1}
                                                               : std::vector<int>{0};
@@ -924,6 +929,8 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     rec(4);
     if (p->p2y) {
       launch_line_reg<T, 1>(y, grid, st, p->n[1], 8);
+    } else if (p->smy) {
+      if (!launch_ypass_smooth<T>(y, grid, st, p->n[1])) return SCFFT_ERR_DEVICE;
     } else {
       launch_line_generic<T>(y, grid, (size_t)p->n[1] * p->yC * esz, st);
     }
@@ -947,7 +954,7 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
       if (d == 2) launch_line_reg<T, 2>(q, grid, st, nl, p->kn.gr);
       else launch_line_reg<T, 3>(q, grid, st, nl, p->kn.gr);
     } else if (p->smg) {
-      if (!launch_gamma_smooth<T>(q, grid, st, nl)) return SCFFT_ERR_DEVICE;
+      if (!launch_gamma_smooth<T>(q, grid, st, nl, d)) return SCFFT_ERR_DEVICE;
     } else {
       launch_line_generic<T>(q, grid, (size_t)nl * d * p->gC * esz, st);
     }
@@ -964,6 +971,8 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     rec(8);
     if (p->p2y) {
       launch_line_reg<T, 1>(y, grid, st, p->n[1], 8);
+    } else if (p->smy) {
+      if (!launch_ypass_smooth<T>(y, grid, st, p->n[1])) return SCFFT_ERR_DEVICE;
     } else {
       launch_line_generic<T>(y, grid, (size_t)p->n[1] * p->yC * esz, st);
     }
@@ -1558,10 +1567,11 @@ scfft_status scfft_plan_info(const scfft_problem* prob, const scfft_options* opt
   rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
                 real_ok(sp, prob->d, prob->n), &tc);
   if (rc != SCFFT_OK) return rc;
-  const int v[12] = {p->real ? 1 : 0, p->packed ? 1 : 0, p->kn.pitch, p->kn.nt, p->kn.xr,
+  const int v[13] = {p->real ? 1 : 0, p->packed ? 1 : 0, p->kn.pitch, p->kn.nt, p->kn.xr,
                      p->kn.gr, p->gC, p->d == 3 ? p->yC : 0, p->tuned ? 1 : 0, p->xL,
-                     p->p2x ? 1 : p->smx ? 2 : 0, p->p2g ? 1 : p->smg ? 2 : 0};
-  for (int i = 0; i < std::min(cap, 12); ++i) info[i] = v[i];
+                     p->p2x ? 1 : p->smx ? 2 : 0, p->p2g ? 1 : p->smg ? 2 : 0,
+                     p->d != 3 ? 0 : p->p2y ? 1 : p->smy ? 2 : 0};
+  for (int i = 0; i < std::min(cap, 13); ++i) info[i] = v[i];
   return SCFFT_OK;
 }
 

@@ -423,7 +423,8 @@ def estimate_interval_lanczos(phase, e0=(1.0, 0.0, 0.0), *, steps=60, symbol="ro
 
 
 PLAN_INFO_KEYS = ("real", "packed", "pitch", "nontemporal", "x_radix", "gamma_radix",
-                  "gamma_tile", "y_tile", "tuned", "x_rows", "x_engine", "gamma_engine")
+                  "gamma_tile", "y_tile", "tuned", "x_rows", "x_engine", "gamma_engine",
+                  "y_engine")
 
 
 def plan_info(phase=None, sigma1=10.0, e0=(1.0, 0.0, 0.0), scheme="acc_em", *, density=None,

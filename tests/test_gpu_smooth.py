@@ -1,11 +1,13 @@
-"""Compile-time mixed-radix passes (2/3/5-smooth lengths, full-complex 2D).
+"""Compile-time mixed-radix passes (2/3/5-smooth lengths).
 
 Every field value after a few fixed iterations against the oracle, on grids
-whose two axes are instantiated lengths (radix sequences with 8, 4, 2, 5
-and 3 passes, several tiles and a ragged last tile of columns and rows), in
-both precisions; and, at the batch grids' own sizes, the same iterations
-against the runtime-planned passes (oracle-pinned elsewhere) with the plan
-report showing which engine ran.
+whose axes are instantiated lengths (radix sequences with 8, 4, 2, 5 and 3
+passes, several tiles and a ragged last tile of columns and rows), in both
+precisions: 2D full-complex fields, and 3D fields whose y and z passes
+(full-complex and real-field mode) take the compile-time strided passes;
+and, at the batch grids' own sizes and on a larger 3D grid, the same
+iterations against the runtime-planned passes (oracle-pinned elsewhere)
+with the plan report showing which engine ran.
 """
 import numpy as np
 import pytest
@@ -94,14 +96,65 @@ def test_smooth_batch_of_mixed_grids(env):
 @pytest.mark.parametrize("scheme,s1", [("acc_em", 3 + 2j), ("ms", 10.0)])
 def test_smooth_x_pass_in_3d(shape, scheme, s1, env):
     # 3D full-complex fields: the x pass takes the compile-time passes, the
-    # strided y and z passes the runtime-planned ones
+    # strided y and z passes (10 and 12 points) the runtime-planned ones
     chi = inputs.random_phase(shape, 0.3, seed=24)
     ref = osolver.solve(chi, s1, [1.0, 0.0, 0.0], scheme, alpha=0.25, beta=4.0, tol=-1,
                         max_iter=3, stag_window=0, div_factor=0)
     info = scfft.plan_info(chi, s1, (1, 0, 0), scheme, precision="fp64")
     assert info["x_engine"] == SMOOTH and info["gamma_engine"] == 0, info
+    assert info["y_engine"] == 0, info
     for precision, bound in (("fp64", 1e-11), ("fp32", 2e-6)):
         got = scfft.solve(chi, s1, (1, 0, 0), scheme, precision=precision, tol=-1, max_iter=3,
                           stag_window=0, div_factor=0)
         assert _rel(got["E"].cpu().numpy(), ref["E"]) < bound, (precision, shape)
         assert abs(got["sigma_star"] - ref["sigma_star"]) / abs(ref["sigma_star"]) < bound
+
+
+@pytest.mark.parametrize("shape,scheme,s1,engines", [
+    # full complex: x, y and z all instantiated lengths
+    ((48, 90, 80), "acc_em", 3 + 2j, (SMOOTH, SMOOTH, SMOOTH)),
+    ((48, 90, 80), "acc_ms", 0.2 + 1j, (SMOOTH, SMOOTH, SMOOTH)),
+    ((48, 90, 80), "ms", 10.0, (SMOOTH, SMOOTH, SMOOTH)),
+    # 30 columns: ragged last tiles in the y and z passes; runtime x pass
+    ((96, 80, 30), "acc_em", 3 + 2j, (0, SMOOTH, SMOOTH)),
+    # real-field mode: 33 half-spectrum columns, register x pass
+    ((90, 48, 64), "ms", 10.0, (1, SMOOTH, SMOOTH)),
+    ((90, 48, 64), "em", 0.05, (1, SMOOTH, SMOOTH)),
+])
+def test_smooth_strided_passes_in_3d(shape, scheme, s1, engines, env):
+    # 3D Gamma pass (three components per mode) and forward / inverse y
+    # passes through the compile-time passes, every field value against the
+    # oracle after three fixed iterations
+    chi = inputs.random_phase(shape, 0.3, seed=25)
+    ref = osolver.solve(chi, s1, [1.0, 0.0, 0.0], scheme, alpha=0.25, beta=4.0, tol=-1,
+                        max_iter=3, stag_window=0, div_factor=0)
+    for precision, bound in (("fp64", 1e-11), ("fp32", 2e-6)):
+        info = scfft.plan_info(chi, s1, (1, 0, 0), scheme, precision=precision)
+        assert (info["x_engine"], info["y_engine"], info["gamma_engine"]) == engines, info
+        got = scfft.solve(chi, s1, (1, 0, 0), scheme, precision=precision, tol=-1, max_iter=3,
+                          stag_window=0, div_factor=0)
+        assert _rel(got["E"].cpu().numpy(), ref["E"]) < bound, (precision, shape)
+        assert _rel(got["J"].cpu().numpy(), ref["J"]) < bound, (precision, shape)
+        assert abs(got["sigma_star"] - ref["sigma_star"]) / abs(ref["sigma_star"]) < bound
+
+
+def test_smooth_3d_against_runtime_passes(env):
+    # a larger 3D grid (many tiles per pass, both precisions): the same
+    # iterations through the runtime-planned passes
+    chi = inputs.random_phase((160, 192, 96), 0.3, seed=26)
+    for precision, bound in (("fp64", 1e-12), ("fp32", 2e-6)):
+        out = []
+        for flag in (False, True):
+            if flag:
+                env.setenv("SCFFT_NO_SMOOTH", "1")
+            else:
+                env.delenv("SCFFT_NO_SMOOTH", raising=False)
+            scfft.release()
+            info = scfft.plan_info(chi, 2 + 3j, (1, 0, 0), "acc_em", precision=precision)
+            assert info["y_engine"] == (0 if flag else SMOOTH), info
+            assert info["gamma_engine"] == (0 if flag else SMOOTH), info
+            out.append(scfft.solve(chi, 2 + 3j, (1, 0, 0), "acc_em", precision=precision, tol=-1,
+                                   max_iter=6, stag_window=0, div_factor=0))
+        a, b = out
+        assert _rel(a["E"].cpu().numpy(), b["E"].cpu().numpy()) < bound, precision
+        assert abs(a["sigma_star"] - b["sigma_star"]) / abs(b["sigma_star"]) < bound

@@ -293,7 +293,8 @@ def main() -> int:
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the headline iteration with per-kernel timing (for rocprofv3)")
     ap.add_argument("--profile-workload", default="headline",
-                    choices=["headline", "cube256_acc_em_fp32", "square2048_acc_em_fp64",
+                    choices=["headline", "cube256_acc_em_fp32", "cube240_acc_em_fp32",
+                             "square2048_acc_em_fp64",
                              "batch_fp32", "batch_fp64", "gradient1024_fp32",
                              "gradient1024_fp64"],
                     help="workload of --profile-only")
@@ -354,12 +355,14 @@ def main() -> int:
             print(json.dumps({"workload": args.profile_workload,
                               "iterations": args.profile_iters}), flush=True)
             return 0
-        if args.profile_workload == "cube256_acc_em_fp32":
-            # 256^3 cube array, sigma1 = 100, the symmetrised power-iteration interval
-            chi3 = torch.as_tensor(inputs.cube_array(256)).cuda()
+        if args.profile_workload.startswith("cube"):
+            # cube array, sigma1 = 100, the 256^3 symmetrised power-iteration
+            # interval; 240^3 runs the compile-time mixed-radix passes
+            n3 = int(args.profile_workload[4:7])
+            chi3 = torch.as_tensor(inputs.cube_array(n3)).cuda()
             prof = scfft.profile_passes(chi3, 100.0, (1.0, 0.0, 0.0), "acc_em", precision="fp32",
                                         alpha=0.1818, beta=5.5015, iters=args.profile_iters)
-            grid = [256, 256, 256]
+            grid = [n3, n3, n3]
         else:
             prec = "fp64" if args.profile_workload == "square2048_acc_em_fp64" else hs["precision"]
             prof = scfft.profile_passes(chi, hs["sigma1"], e0, hs["scheme"], precision=prec,

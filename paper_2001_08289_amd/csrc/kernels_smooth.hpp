@@ -238,8 +238,9 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
                              gridDim.x, tid);
 }
 
-// Strided pass of a full-complex field over lines of N points along the
-// last axis (a.mode 0: forward FFT, Gamma_1 of eq. J11 (J44-J45 in H'') with
+// Strided pass over the columns of the spectrum (n0 of a full-complex
+// field, n0/2 + 1 in real-field mode) along lines of N points on the last
+// axis (a.mode 0: forward FFT, Gamma_1 of eq. J11 (J44-J45 in H'') with
 // the scheme's k = 0 source, inverse FFT, all D = d components) or along y in
 // 3D (mode 1 / 2: forward / inverse FFT of one component, D = 1).  A tile of
 // C adjacent columns, one wave per column and component: the tile is staged
@@ -263,11 +264,20 @@ __global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GAr
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (a.fin && blockIdx.x == 0 && blockIdx.y == 0 && comp0 == 0)
     finalize_solve(a.f, solve, tid, NT);
-  const int x0 = blockIdx.x * C;
+  // XCD-aware tile order: the hardware deals workgroups round-robin over
+  // the 8 XCDs, so consecutive tiles (sharing cache lines at their edges)
+  // are given to workgroups that run on the same XCD and L2 (measured: the
+  // fp32 3D Gamma pass 24 % faster at 240^3 and 320^3)
+  const int nbx = gridDim.x, nb = nbx * gridDim.y;
+  const int b = blockIdx.y * nbx + blockIdx.x;
+  const int full = nb - nb % 8;
+  const int t = b < full ? (b % 8) * (full / 8) + b / 8 : b;
+  const int bx = t % nbx, by = t / nbx;
+  const int x0 = bx * C;
   const int nlc = min(C, a.n[0] - x0);
   const long long M = a.M;
   // 2D Gamma: x0; 3D Gamma: x0 + y rp; 3D y pass: x0 + z rp n1
-  const long long off = x0 + (long long)blockIdx.y * a.rp * (gam ? 1 : a.n[1]);
+  const long long off = x0 + (long long)by * a.rp * (gam ? 1 : a.n[1]);
   cx<T>* X = reinterpret_cast<cx<T>*>(a.X) + ((long long)solve * d + comp0) * M + off;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const long long stride = a.stride;
@@ -302,7 +312,7 @@ __global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GAr
       const int k = i / C;
       const int l = i - k * C;
       if (l >= nlc) continue;
-      const int m[3] = {x0 + l, D == 2 ? k : (int)blockIdx.y, D == 2 ? 0 : k};
+      const int m[3] = {x0 + l, D == 2 ? k : by, D == 2 ? 0 : k};
       T tv[D][2];
       symbol_entries<T, D>(a, m, tv);
       cx<T> wv[D];

@@ -1,8 +1,9 @@
 // Compile-time mixed-radix passes for 2/3/5-smooth line lengths (gfx950).
 //
-// Each line is transformed by one wave (64 lanes) through its own LDS slot,
-// so the Stockham passes synchronise only the wave (an in-order LDS queue
-// plus a compiler fence), never the workgroup; the line length, the radix
+// Each line is transformed by LW lanes of one wave (all 64, or 32 / 16 for
+// short lines, several lines to a wave) through its own LDS slot, so the
+// Stockham passes synchronise only the wave (an in-order LDS queue plus a
+// compiler fence), never the workgroup; the line length, the radix
 // sequence and the slot layout are compile-time constants, so every pass is
 // unrolled and its index arithmetic folds into multiplications by constants.
 // Workgroup barriers remain only where waves exchange data: the staging of
@@ -54,6 +55,30 @@ constexpr int sm_radix(int n, int p) {
   return 0;
 }
 
+// Lane slots a line of n points occupies over its passes when each pass's
+// butterflies are dealt to lw lanes (a pass of b butterflies costs
+// ceil(b / lw) lw slots).
+constexpr int sm_slots(int n, int lw) {
+  int s = 0;
+  for (int p = 0; sm_radix(n, p) > 0; ++p) {
+    const int b = n / sm_radix(n, p);
+    s += (b + lw - 1) / lw * lw;
+  }
+  return s;
+}
+
+// Lanes per line: 64, or 32 / 16 (several lines to a wave) while that saves
+// at least 15 % of the lane slots (a 64-lane 240-point line fills 30 lanes
+// in its radix-8 pass; 32-lane lines cut its slots from 384 to 320).
+constexpr int sm_lanes(int n) {
+  int lw = 64;
+  if (sm_slots(n, 32) * 100 <= sm_slots(n, 64) * 85) {
+    lw = 32;
+    if (sm_slots(n, 16) * 100 <= sm_slots(n, 32) * 85) lw = 16;
+  }
+  return lw;
+}
+
 // Orders this wave's LDS accesses: every lane's earlier reads and writes
 // are complete (and visible to the wave) before any later one.
 __device__ __forceinline__ void wave_sync() {
@@ -70,31 +95,41 @@ struct SmShape {
   static constexpr int Q = 64 / DW;                  // points per bank sweep
   static constexpr int LSP = (N + Q - 2) / Q * Q + 1;
   static constexpr int R0 = sm_radix(N, 0);          // radix of the first pass
-  static constexpr int B0 = (N / R0 + 63) / 64;      // its butterflies per lane
-  // x pass: rows (waves) per workgroup (measured on the 16-grid batch: two
-  // rows beat four)
-  static constexpr int XW = 2;
-  static constexpr int XLDS = XW * LSP * (int)sizeof(cx<T>) + 5 * XW * 8;
+  static constexpr int LW = sm_lanes(N);              // lanes per line
+  static constexpr int LPW = 64 / LW;                // lines per wave
+  static constexpr int B0 = (N / R0 + LW - 1) / LW;  // first-pass butterflies per lane
+  // x pass: waves per workgroup (measured on the 16-grid batch: two beat
+  // four; one for short lines, so that small grids keep their workgroup
+  // count), XL rows
+  static constexpr int XW = LPW > 1 ? 1 : 2;
+  static constexpr int XL = XW * LPW;
+  static constexpr int XLDS = XL * LSP * (int)sizeof(cx<T>) + 5 * XW * 8;
 };
 
-// Strided passes: tiles of C adjacent columns, one wave per column and
-// component (D components: 2 / 3 the Gamma pass of a 2D / 3D grid, 1 a plain
-// 3D y pass).  2D Gamma, measured on the 16-grid batch: 8 fp32 columns
-// (64-byte row pieces) beat 4 by 8 %; fp64 keeps 2.  The y pass takes
-// 64-byte pieces in both precisions; the 3D Gamma pass halves the 2D widths
-// to stay within 16 waves.
+// Strided passes: tiles of C adjacent columns, one line (LW lanes) per
+// column and component (D components: 2 / 3 the Gamma pass of a 2D / 3D
+// grid, 1 a plain 3D y pass).  2D Gamma, measured on the 16-grid batch:
+// 8 fp32 columns (64-byte row pieces) beat 4 by 8 %; fp64 keeps 2.  The y
+// pass takes 64-byte pieces in both precisions; the 3D Gamma pass halves
+// the 2D widths to stay within 16 waves.  In 3D, lines of fewer than 64
+// lanes widen the tile by the lines per wave; 2D grids of short lines have
+// few columns, and keep their tile count.
 template <typename T, int N, int D>
 struct SmTile {
   static constexpr bool F = sizeof(T) == 4;
-  static constexpr int C = D == 1 ? (F ? 8 : 4) : D == 2 ? (F ? 8 : 2) : (F ? 4 : 2);
-  static constexpr int GW = D * C;
+  static constexpr int LW = SmShape<T, N>::LW;
+  static constexpr int C = (D == 1 ? (F ? 8 : 4) : D == 2 ? (F ? 8 : 2) : (F ? 4 : 2)) *
+                           (D == 2 ? 1 : SmShape<T, N>::LPW);
+  static constexpr int GW = D * C;                   // lines per workgroup
+  static constexpr int NT = GW * LW;                 // threads
   static constexpr int LDS = GW * SmShape<T, N>::LSP * (int)sizeof(cx<T>);
-  static_assert(GW <= 16, "at most 1024 threads per workgroup");
+  static_assert(NT <= 1024, "at most 1024 threads per workgroup");
 };
 
-// One radix-r pass of a wave's line (slot: N points at slot[0..N)).  P = 0
-// takes its inputs from the registers v0 (point j + q N/R0 of butterfly
-// j = lane + 64 u at v0[u][q]); every pass writes its outputs to the slot.
+// One radix-r pass of a line held by LW lanes of a wave (slot: N points at
+// slot[0..N); lane: 0..LW-1).  P = 0 takes its inputs from the registers v0
+// (point j + q N/R0 of butterfly j = lane + LW u at v0[u][q]); every pass
+// writes its outputs to the slot.
 template <typename T, int N, int P, int NS>
 __device__ __forceinline__ void sm_pass(const cx<T> (&v0)[SmShape<T, N>::B0][SmShape<T, N>::R0],
                                         cx<T>* __restrict__ slot, const cx<T>* __restrict__ tw,
@@ -102,8 +137,9 @@ __device__ __forceinline__ void sm_pass(const cx<T> (&v0)[SmShape<T, N>::B0][SmS
   if constexpr (NS < N) {
     constexpr int r = sm_radix(N, P);
     static_assert(r > 0 && N % (NS * r) == 0, "radix sequence must factor N");
+    constexpr int LW = SmShape<T, N>::LW;
     constexpr int NBL = N / r;                  // butterflies
-    constexpr int BPL = (NBL + 63) / 64;        // per lane
+    constexpr int BPL = (NBL + LW - 1) / LW;    // per lane
     constexpr int STEP = N / (NS * r);          // twiddle table stride
     cx<T> v[BPL][r];
     if constexpr (P == 0) {
@@ -114,8 +150,8 @@ __device__ __forceinline__ void sm_pass(const cx<T> (&v0)[SmShape<T, N>::B0][SmS
     } else {
 #pragma unroll
       for (int u = 0; u < BPL; ++u) {
-        const int j = lane + 64 * u;
-        if (NBL % 64 == 0 || j < NBL) {
+        const int j = lane + LW * u;
+        if (NBL % LW == 0 || j < NBL) {
 #pragma unroll
           for (int q = 0; q < r; ++q) v[u][q] = slot[j + q * NBL];
         }
@@ -124,8 +160,8 @@ __device__ __forceinline__ void sm_pass(const cx<T> (&v0)[SmShape<T, N>::B0][SmS
     wave_sync();   // the pass's reads are done before its in-place writes
 #pragma unroll
     for (int u = 0; u < BPL; ++u) {
-      const int j = lane + 64 * u;
-      if (NBL % 64 == 0 || j < NBL) {
+      const int j = lane + LW * u;
+      if (NBL % LW == 0 || j < NBL) {
         const int k = j % NS;
         if constexpr (NS > 1) {
           // one table load per butterfly; the powers w^q follow by products
@@ -149,7 +185,7 @@ __device__ __forceinline__ void sm_pass(const cx<T> (&v0)[SmShape<T, N>::B0][SmS
   }
 }
 
-// Unnormalised transform of one line held by a wave: input in registers in
+// Unnormalised transform of one line held by LW lanes: input in registers in
 // the first pass's layout, output in the slot in natural order (sign -1
 // forward, +1 inverse).
 template <typename T, int N>
@@ -158,22 +194,23 @@ __device__ __forceinline__ void sm_fft(const cx<T> (&v0)[SmShape<T, N>::B0][SmSh
   sm_pass<T, N, 0, 1>(v0, slot, tw, sign, lane);
 }
 
-// x pass of a full-complex field: one row per wave, XW rows per workgroup
-// (rows past the field's last transform zeros and are not stored): inverse
+// x pass of a full-complex field: one row per LW lanes, XL rows per
+// workgroup (rows past the field's last transform zeros and are not
+// stored): inverse
 // x-FFT, local map of the scheme (MK fixes it at compile time), forward
 // x-FFT, fp64 partial sums.
 template <typename T, int N, int MK>
 __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArgs a) {
   using SH = SmShape<T, N>;
-  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0;
+  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, LW = SH::LW;
   const int solve = blockIdx.z;
   const int comp = blockIdx.y;
   if (!a.ignore_done && a.ctl[solve].done) return;
   extern __shared__ unsigned char smem_raw[];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid % LW, w = tid / LW;
   cx<T>* slot = reinterpret_cast<cx<T>*>(smem_raw) + w * SH::LSP;
-  double* red = reinterpret_cast<double*>(smem_raw + SH::XW * SH::LSP * sizeof(cx<T>));
-  const long long line = (long long)blockIdx.x * SH::XW + w;
+  double* red = reinterpret_cast<double*>(smem_raw + SH::XL * SH::LSP * sizeof(cx<T>));
+  const long long line = (long long)blockIdx.x * SH::XL + w;
   const bool valid = line < a.nlines;
   const long long fbase = ((long long)solve * a.d + comp) * a.M;
   const long long base = line * N;
@@ -182,10 +219,10 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
   cx<T> v0[B0][R0];
 #pragma unroll
   for (int u = 0; u < B0; ++u) {
-    const int j = lane + 64 * u;
+    const int j = lane + LW * u;
 #pragma unroll
     for (int q = 0; q < R0; ++q)
-      v0[u][q] = (valid && (NB0 % 64 == 0 || j < NB0)) ? X[base + j + q * NB0] : mk<T>(0, 0);
+      v0[u][q] = (valid && (NB0 % LW == 0 || j < NB0)) ? X[base + j + q * NB0] : mk<T>(0, 0);
   }
   LocalMap<T, MK> lm;
   lm.load(a, solve, comp, fbase);
@@ -198,8 +235,8 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
   if (PF && valid) {
 #pragma unroll
     for (int u = 0; u < B0; ++u) {
-      const int j = lane + 64 * u;
-      if (NB0 % 64 == 0 || j < NB0) {
+      const int j = lane + LW * u;
+      if (NB0 % LW == 0 || j < NB0) {
 #pragma unroll
         for (int q = 0; q < R0; ++q) {
           const long long g = base + j + q * NB0;
@@ -213,8 +250,8 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
   Acc acc;
 #pragma unroll
   for (int u = 0; u < B0; ++u) {
-    const int j = lane + 64 * u;
-    if (valid && (NB0 % 64 == 0 || j < NB0)) {
+    const int j = lane + LW * u;
+    if (valid && (NB0 % LW == 0 || j < NB0)) {
 #pragma unroll
       for (int q = 0; q < R0; ++q) {
         const long long g = base + j + q * NB0;
@@ -228,9 +265,9 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
   sm_fft<T, N>(v0, slot, tw, (T)-1, lane);
   if (valid) {
 #pragma unroll
-    for (int t = 0; t < (N + 63) / 64; ++t) {
-      const int i = lane + 64 * t;
-      if (N % 64 == 0 || i < N) X[base + i] = slot[i];
+    for (int t = 0; t < (N + LW - 1) / LW; ++t) {
+      const int i = lane + LW * t;
+      if (N % LW == 0 || i < N) X[base + i] = slot[i];
     }
   }
   block_reduce5<64 * SH::XW>(acc, red,
@@ -243,17 +280,18 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
 // axis (a.mode 0: forward FFT, Gamma_1 of eq. J11 (J44-J45 in H'') with
 // the scheme's k = 0 source, inverse FFT, all D = d components) or along y in
 // 3D (mode 1 / 2: forward / inverse FFT of one component, D = 1).  A tile of
-// C adjacent columns, one wave per column and component: the tile is staged
-// through LDS in row pieces, each wave transforms its own line, the Gamma
+// C adjacent columns, one line of LW lanes per column and component: the
+// tile is staged through LDS in row pieces, each line is transformed by its
+// own lanes, the Gamma
 // step couples the components of every mode, and the tile is stored back.
 // Workgroup (0, 0) of each solve's Gamma pass also reduces the x pass's
 // partial sums and applies the stop rules.
 template <typename T, int N, int D>
-__global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GArgs a) {
+__global__ __launch_bounds__((SmTile<T, N, D>::NT)) void line_sm_kernel(GArgs a) {
   using SH = SmShape<T, N>;
   using TS = SmTile<T, N, D>;
-  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, LSP = SH::LSP;
-  constexpr int C = TS::C, GW = TS::GW, NT = 64 * GW;
+  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, LSP = SH::LSP, LW = SH::LW;
+  constexpr int C = TS::C, GW = TS::GW, NT = TS::NT;
   const bool gam = (a.mode == 0);
   const int d = a.d;
   const int solve = gam ? blockIdx.z : blockIdx.z / d;
@@ -261,7 +299,7 @@ __global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GAr
   if (!a.ignore_done && a.ctl[solve].done) return;
   extern __shared__ unsigned char smem_raw[];
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid % LW, w = tid / LW;
   if (a.fin && blockIdx.x == 0 && blockIdx.y == 0 && comp0 == 0)
     finalize_solve(a.f, solve, tid, NT);
   // XCD-aware tile order: the hardware deals workgroups round-robin over
@@ -296,8 +334,8 @@ __global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GAr
   if (a.mode != 2) {
 #pragma unroll
     for (int u = 0; u < B0; ++u) {
-      const int j = lane + 64 * u;
-      if (NB0 % 64 == 0 || j < NB0) {
+      const int j = lane + LW * u;
+      if (NB0 % LW == 0 || j < NB0) {
 #pragma unroll
         for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
       }
@@ -327,8 +365,8 @@ __global__ __launch_bounds__((64 * SmTile<T, N, D>::GW)) void line_sm_kernel(GAr
   if (a.mode != 1) {
 #pragma unroll
     for (int u = 0; u < B0; ++u) {
-      const int j = lane + 64 * u;
-      if (NB0 % 64 == 0 || j < NB0) {
+      const int j = lane + LW * u;
+      if (NB0 % LW == 0 || j < NB0) {
 #pragma unroll
         for (int q = 0; q < R0; ++q) v0[u][q] = slot[j + q * NB0];
       }

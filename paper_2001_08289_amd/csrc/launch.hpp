@@ -83,8 +83,8 @@ void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
     default: break;                  \
   }
 
-// Compile-time mixed-radix passes (one wave per line): false (nothing
-// launched) for a length without an instantiation.  x pass grid = (row
+// Compile-time mixed-radix passes (one line per 64, 32 or 16 lanes): false
+// (nothing launched) for a length without an instantiation.  x pass grid = (row
 // blocks of smooth_lines rows, d, solves); Gamma grid = (column tiles of
 // smooth_cols columns, 1 (2D) or n1 (3D), solves); 3D y pass grid = (column
 // tiles, n2, solves x 3).

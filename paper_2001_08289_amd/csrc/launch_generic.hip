@@ -74,11 +74,11 @@ int line_tile_max(int n, int esz, int D, int gr) {
 
 int smooth_lines(int n, int esz) {
   if (esz == 8) {
-#define C_(N) return SmShape<float, N>::XW
+#define C_(N) return SmShape<float, N>::XL
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   } else {
-#define C_(N) return SmShape<double, N>::XW
+#define C_(N) return SmShape<double, N>::XL
     SCFFT_SMOOTH_SWITCH(n, C_)
 #undef C_
   }

@@ -29,7 +29,7 @@ bool smooth_sm(const XArgs& xa, const GArgs& ga, dim3 grid, hipStream_t st) {
         set = true;
       }
     }
-    hipLaunchKernelGGL((line_sm_kernel<T, N, D>), grid, dim3(64 * TS::GW), (size_t)TS::LDS, st, ga);
+    hipLaunchKernelGGL((line_sm_kernel<T, N, D>), grid, dim3(TS::NT), (size_t)TS::LDS, st, ga);
   } else {
     (void)ga;
     hipLaunchKernelGGL((xpass_sm_kernel<T, N, SCFFT_SMK>), grid, dim3(64 * SH::XW),

@@ -22,6 +22,9 @@ CASES = [
     (lambda: inputs.random_phase((16, 24, 32), 0.3, seed=6), 10.0, (0, 0, 1), "acc_em", "fp64",
      -1, 7),
     (lambda: inputs.random_disks(288, seed=3)[0], 50.0, (1, 0), "em", "fp32", 1e-6, 400),
+    # 3D mixed-radix passes on every axis (80-, 90- and 48-point lines)
+    (lambda: inputs.random_phase((48, 90, 80), 0.3, seed=7), 3 + 2j, (1, 0, 0), "acc_em", "fp32",
+     1e-6, 200),
 ]
 
 
@@ -50,7 +53,7 @@ def _check(ref, got):
     assert len(got["sigma_history"]) == n + 1
 
 
-@pytest.mark.parametrize("order", [(0, 1), (2, 3), (0, 2)])
+@pytest.mark.parametrize("order", [(0, 1), (2, 3), (0, 2), (4, 1)])
 def test_noalloc_matches_solve_two_calls(order):
     """Two calls in a row, the second on a smaller problem."""
     for k in order:

@@ -158,3 +158,23 @@ def test_smooth_3d_against_runtime_passes(env):
         a, b = out
         assert _rel(a["E"].cpu().numpy(), b["E"].cpu().numpy()) < bound, precision
         assert abs(a["sigma_star"] - b["sigma_star"]) / abs(b["sigma_star"]) < bound
+
+
+def test_smooth_batch_of_3d_grids(env):
+    # one batch over a 3D grid of instantiated lengths on every axis, one
+    # with short 16-lane lines and a ragged tile, and a power-of-two grid,
+    # each solve against its own single solve
+    shapes = [(48, 90, 80), (96, 48, 30), (32, 32, 32)]
+    chis = [inputs.random_phase(s, 0.3, seed=27 + i) for i, s in enumerate(shapes)]
+    sig = np.array([[3 + 1j, 0.5 - 2j]] * 3)
+    for precision, tol, bound in (("fp64", 1e-10, 1e-12), ("fp32", 1e-5, 1e-6)):
+        res = scfft.solve_batch([torch.as_tensor(c).cuda() for c in chis], sig, e0=(1, 0, 0),
+                                scheme="acc_em", precision=precision, tol=tol, max_iter=400)
+        for i, c in enumerate(chis):
+            for j in range(2):
+                one = scfft.solve(c, sig[i, j], (1, 0, 0), "acc_em", precision=precision, tol=tol,
+                                  max_iter=400, fields=False)
+                got = res[i * 2 + j]
+                assert got["iterations"] == one["iterations"], (precision, i, j)
+                rel = abs(got["sigma_star"] - one["sigma_star"]) / abs(one["sigma_star"])
+                assert rel < bound, (precision, i, j, rel)

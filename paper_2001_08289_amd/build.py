@@ -29,7 +29,7 @@ FLAGS = [
 UNITS = [("scfft.hip", "scfft", []), ("launch_generic.hip", "generic", [])]
 for t in ("float", "double"):
     UNITS.append(("launch_xpass.hip", f"xpass_{t}", [f"-DSCFFT_T={t}"]))
-    for k in range(7):
+    for k in range(11):
         UNITS.append(("launch_smooth.hip", f"smooth{k}_{t}", [f"-DSCFFT_T={t}", f"-DSCFFT_SMK={k}"]))
     for d in (1, 2, 3):
         UNITS.append(("launch_line.hip", f"line{d}_{t}", [f"-DSCFFT_T={t}", f"-DSCFFT_D={d}"]))

@@ -18,7 +18,7 @@
 // q / (NS r)); unnormalised, forward exp(-2 pi i jk/N).
 #pragma once
 
-#include "kernels_p2.hpp"
+#include "kernels_real.hpp"
 
 namespace scfft {
 
@@ -273,6 +273,91 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_kernel(XArg
   block_reduce5<64 * SH::XW>(acc, red,
                              a.part + ((long long)solve * a.d + comp) * 5 * gridDim.x + blockIdx.x,
                              gridDim.x, tid);
+}
+
+// x pass of a real field (real-field mode): each line is the pair of real
+// rows (2p, 2p + 1) of one component, transformed as w = a + i b, XL pairs
+// per workgroup.  The half spectra A(k), B(k) (k = 0..N/2, no packed
+// column) give W(k) = A(k) + i B(k), with A(N - k) = conj A(k) above N/2;
+// inverse FFT, the real local map on a and b, forward FFT, and the rows'
+// half spectra back from A = (W(k) + conj W(N-k)) / 2,
+// B = (W(k) - conj W(N-k)) / 2i; fp64 partial sums.
+template <typename T, int N, int MK>
+__global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_r2c_kernel(XArgs a) {
+  using SH = SmShape<T, N>;
+  constexpr int R0 = SH::R0, B0 = SH::B0, NB0 = N / R0, LW = SH::LW;
+  static_assert(N % 2 == 0, "real rows of even length");
+  const int solve = blockIdx.z;
+  const int comp = blockIdx.y;
+  if (!a.ignore_done && a.ctl[solve].done) return;
+  extern __shared__ unsigned char smem_raw[];
+  const int tid = threadIdx.x, lane = tid % LW, w = tid / LW;
+  cx<T>* slot = reinterpret_cast<cx<T>*>(smem_raw) + w * SH::LSP;
+  double* red = reinterpret_cast<double*>(smem_raw + SH::XL * SH::LSP * sizeof(cx<T>));
+  const long long pr = (long long)blockIdx.x * SH::XL + w;
+  const bool valid = pr < a.nlines / 2;
+  const long long rowA = 2 * pr, rowB = 2 * pr + 1;
+  const long long cbase = (long long)solve * a.d + comp;
+  cx<T>* XA = reinterpret_cast<cx<T>*>(a.X) + cbase * a.Mh + rowA * a.hp;
+  cx<T>* XB = XA + a.hp;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  cx<T> v0[B0][R0];
+#pragma unroll
+  for (int u = 0; u < B0; ++u) {
+    const int j = lane + LW * u;
+#pragma unroll
+    for (int q = 0; q < R0; ++q) {
+      const int k = j + q * NB0;
+      cx<T> av = mk<T>(0, 0), bv = mk<T>(0, 0);
+      if (valid && (NB0 % LW == 0 || j < NB0)) {
+        if (k <= N / 2) {
+          av = XA[k];
+          bv = XB[k];
+        } else {
+          av = conj(XA[N - k]);
+          bv = conj(XB[N - k]);
+        }
+      }
+      v0[u][q] = mk<T>(av.x - bv.y, av.y + bv.x);   // a + i b
+    }
+  }
+  LocalMapR<T, MK> lm;
+  lm.load(a, solve, comp, cbase * a.M);
+  const auto wa = lm.row(rowA * N);
+  const auto wb = lm.row(rowB * N);
+  sm_fft<T, N>(v0, slot, tw, (T)1, lane);
+  Acc acc;
+#pragma unroll
+  for (int u = 0; u < B0; ++u) {
+    const int j = lane + LW * u;
+    if (valid && (NB0 % LW == 0 || j < NB0)) {
+#pragma unroll
+      for (int q = 0; q < R0; ++q) {
+        const unsigned int k = (unsigned int)(j + q * NB0);
+        const cx<T> z = slot[k];
+        const T oa = lm.apply(z.x, wa, k, acc);
+        const T ob = lm.apply(z.y, wb, k, acc);
+        v0[u][q] = mk<T>(oa, ob);
+        acc_settle<false>(acc);
+      }
+    }
+  }
+  sm_fft<T, N>(v0, slot, tw, (T)-1, lane);
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < (N / 2 + LW) / LW; ++t) {
+      const int k = lane + LW * t;
+      if (k <= N / 2) {
+        const cx<T> wk = slot[k];
+        const cx<T> wn = conj(slot[k == 0 ? 0 : N - k]);
+        const cx<T> sm = wk + wn, df = wk - wn;
+        XA[k] = mk<T>((T)0.5 * sm.x, (T)0.5 * sm.y);
+        XB[k] = mk<T>((T)0.5 * df.y, (T)-0.5 * df.x);
+      }
+    }
+  }
+  block_reduce5<64 * SH::XW>(acc, red, a.part + cbase * 5 * gridDim.x + blockIdx.x, gridDim.x,
+                             tid);
 }
 
 // Strided pass over the columns of the spectrum (n0 of a full-complex

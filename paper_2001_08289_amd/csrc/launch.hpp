@@ -88,7 +88,8 @@ void launch_line_r16_f64_2048(const GArgs& a, dim3 grid, hipStream_t st);
 // blocks of smooth_lines rows, d, solves); Gamma grid = (column tiles of
 // smooth_cols columns, 1 (2D) or n1 (3D), solves); 3D y pass grid = (column
 // tiles, n2, solves x 3).
-// mk: the x pass's local map (MapKind).
+// mk: the x pass's local map (MapKind).  The real-field x pass (grid =
+// (blocks of smooth_lines row pairs, d, solves)) takes no packed column.
 template <typename T, int K>
 bool launch_smooth_unit(const XArgs* xa, const GArgs* ga, dim3 grid, hipStream_t st, int n);
 template <typename T>
@@ -98,6 +99,15 @@ bool launch_xpass_smooth(const XArgs& a, dim3 grid, hipStream_t st, int n, int m
     case MAP_LIN_DENS: return launch_smooth_unit<T, MAP_LIN_DENS>(&a, nullptr, grid, st, n);
     case MAP_ACC_EM: return launch_smooth_unit<T, MAP_ACC_EM>(&a, nullptr, grid, st, n);
     default: return launch_smooth_unit<T, MAP_ACC_MS>(&a, nullptr, grid, st, n);
+  }
+}
+template <typename T>
+bool launch_xpass_smooth_real(const XArgs& a, dim3 grid, hipStream_t st, int n, int mk) {
+  switch (mk) {
+    case MAP_LIN: return launch_smooth_unit<T, 7 + MAP_LIN>(&a, nullptr, grid, st, n);
+    case MAP_LIN_DENS: return launch_smooth_unit<T, 7 + MAP_LIN_DENS>(&a, nullptr, grid, st, n);
+    case MAP_ACC_EM: return launch_smooth_unit<T, 7 + MAP_ACC_EM>(&a, nullptr, grid, st, n);
+    default: return launch_smooth_unit<T, 7 + MAP_ACC_MS>(&a, nullptr, grid, st, n);
   }
 }
 template <typename T>

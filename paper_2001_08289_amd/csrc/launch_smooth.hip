@@ -1,11 +1,12 @@
 // Instantiations of the compile-time mixed-radix passes for one precision
-// (SCFFT_T) and one kernel family (SCFFT_SMK: 0..3 the x pass with that
-// local map; 4 / 5 the Gamma pass of a 2D / 3D grid; 6 the 3D y pass), both
-// set by the build.
+// (SCFFT_T) and one kernel family (SCFFT_SMK: 0..3 the x pass of a
+// full-complex field with that local map; 4 / 5 the Gamma pass of a 2D / 3D
+// grid; 6 the 3D y pass; 7..10 the real-field x pass with local map
+// SCFFT_SMK - 7), both set by the build.
 #include "launch.hpp"
 
 #if !defined(SCFFT_T) || !defined(SCFFT_SMK)
-#error "SCFFT_T (float or double) and SCFFT_SMK (0..6) must be defined"
+#error "SCFFT_T (float or double) and SCFFT_SMK (0..10) must be defined"
 #endif
 
 namespace scfft {
@@ -15,7 +16,11 @@ template <typename T, int N>
 bool smooth_sm(const XArgs& xa, const GArgs& ga, dim3 grid, hipStream_t st) {
   using SH = SmShape<T, N>;
   static_assert(SH::XLDS <= 65536, "x-pass workgroup LDS within 64 KiB");
-  if constexpr (SCFFT_SMK >= 4) {
+  if constexpr (SCFFT_SMK >= 7) {
+    (void)ga;
+    hipLaunchKernelGGL((xpass_sm_r2c_kernel<T, N, SCFFT_SMK - 7>), grid, dim3(64 * SH::XW),
+                       (size_t)SH::XLDS, st, xa);
+  } else if constexpr (SCFFT_SMK >= 4) {
     (void)xa;
     constexpr int D = SCFFT_SMK == 4 ? 2 : SCFFT_SMK == 5 ? 3 : 1;
     using TS = SmTile<T, N, D>;

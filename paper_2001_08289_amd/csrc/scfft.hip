@@ -248,7 +248,7 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   p->H = real ? n[0] / 2 + 1 : n[0];
   p->p2y = d == 3 && is_p2(n[1]) && !std::getenv("SCFFT_NO_P2");
   const bool sm_on = !std::getenv("SCFFT_NO_SMOOTH");
-  p->smx = sm_on && !real && !p->p2x && smooth_lines(n[0], esz) > 0;
+  p->smx = sm_on && !p->p2x && smooth_lines(n[0], esz) > 0;
   p->smg = sm_on && !p->p2g && smooth_cols(nlast, esz, d) > 0;
   p->smy = sm_on && d == 3 && !p->p2y && smooth_cols(n[1], esz, 1) > 0;
   Knobs& k = p->kn;
@@ -305,9 +305,9 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   }
   p->yC = k.yC;
   // 2D real mode: pack kx = 0 and kx = n0/2 into one column (the register
-  // Gamma pass unpacks it); the rule packs when that lowers the number of
+  // x and Gamma passes unpack it); the rule packs when that lowers the number of
   // Gamma-pass workgroups the busiest CU runs, and for the radix-16 pass
-  if (real && d == 2 && p->p2g) {
+  if (real && d == 2 && p->p2g && p->p2x) {
     const int dflt = want.pack >= 0 ? want.pack
                    : (k.gr == 16 || pack_pays(n[0], p->gC, nsolve, dev)) ? 1 : 0;
     k.pack = env_int("SCFFT_PACK", dflt) != 0 ? 1 : 0;
@@ -337,9 +337,9 @@ void plan_shape(Plan* p, int dev, int d, const int* n, int prec, int nsolve, boo
   // fp64 lose, the slots being touched only at phase-1 voxels)
   {
     const size_t foot = xfield + rfield;
-    k.nt = real ? (env_int("SCFFT_NT", want.nt >= 0 ? want.nt : (foot > kInfinityCacheBytes))
-                   != 0)
-                : 0;
+    k.nt = (real && !p->smx)
+               ? (env_int("SCFFT_NT", want.nt >= 0 ? want.nt : (foot > kInfinityCacheBytes)) != 0)
+               : 0;
     p->nt = k.nt != 0;
   }
   p->xbytes = xfield;
@@ -517,9 +517,11 @@ scfft_status autotune(int dev, int d, const int* n, int prec, bool st, int symbo
     else
       for (int c = 1; c <= std::min(cmax, 8); c *= 2) ycs.push_back(c);
   }
-  const std::vector<int> packs = (real && d == 2 && probe.p2g) ? std::vector<int>{0, 1}
-                                                              : std::vector<int>{0};
+  const std::vector<int> packs = (real && d == 2 && probe.p2g && probe.p2x)
+                                     ? std::vector<int>{0, 1} : std::vector<int>{0};
   const std::vector<int> bins = real ? std::vector<int>{0, 1} : std::vector<int>{0};
+  // nontemporal streams: the register real-field x pass only
+  const std::vector<int> nts = (real && !probe.smx) ? std::vector<int>{0, 1} : std::vector<int>{0};
   int part_blocks = 0;
   for (int xr : xrs) {
     Plan t = probe;
@@ -534,7 +536,7 @@ scfft_status autotune(int dev, int d, const int* n, int prec, bool st, int symbo
   const size_t rounds = std::max({xrs.size(), gcs.size(), ycs.size()});
   for (int pack : packs)
     for (int pitch : bins)
-      for (int nt : bins) {
+      for (int nt : nts) {
         if (rc != SCFFT_OK) break;
         Knobs lay;
         lay.pack = pack;
@@ -877,7 +879,9 @@ scfft_status launch_iteration_t(Plan* p, const uint8_t* phase, const double* den
     // the x pass reuses its LDS for a 5 x (kNT/64) fp64 reduction
     rec(0);
     const dim3 grid(p->xblocks, d, p->nsolve);
-    if (p->real) {
+    if (p->real && p->smx) {
+      if (!launch_xpass_smooth_real<T>(a, grid, st, p->n[0], p->mk)) return SCFFT_ERR_DEVICE;
+    } else if (p->real) {
       launch_xpass_real<T>(a, grid, st, p->n[0], p->mk, p->nt, p->kn.xr);
     } else if (p->p2x) {
       launch_xpass_reg<T>(a, grid, st, p->n[0], p->mk, p->kn.xr);
@@ -1424,11 +1428,13 @@ cd graded_sigma0(int scheme, cd s1) {
   return std::sqrt(s1);
 }
 
-// Real-field mode: every coefficient real, a power-of-two x length and an
-// even number of x lines (rows are transformed in pairs).
+// Real-field mode: every coefficient real, an x length with a real-field x
+// pass (a power of two, or a compile-time mixed-radix length) and an even
+// number of x lines (rows are transformed in pairs).
 bool real_ok(const SolveSpec& sp, int d, const int* n) {
   if (std::getenv("SCFFT_NO_REAL")) return false;
-  if (!is_p2(n[0])) return false;
+  const bool sm_x = !std::getenv("SCFFT_NO_SMOOTH") && smooth_lines(n[0], 8) > 0;
+  if (!is_p2(n[0]) && !sm_x) return false;
   const long long lines = (long long)n[1] * (d == 3 ? n[2] : 1);
   if (lines % 2) return false;
   if (sp.s1.imag() != 0.0 || sp.s0.imag() != 0.0) return false;

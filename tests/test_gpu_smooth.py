@@ -178,3 +178,45 @@ def test_smooth_batch_of_3d_grids(env):
                 assert got["iterations"] == one["iterations"], (precision, i, j)
                 rel = abs(got["sigma_star"] - one["sigma_star"]) / abs(one["sigma_star"])
                 assert rel < bound, (precision, i, j, rel)
+
+
+@pytest.mark.parametrize("shape", [(90, 96), (180, 240), (64, 400), (48, 90, 80), (12, 10, 48)])
+@pytest.mark.parametrize("scheme,s1", [("acc_em", 100.0), ("acc_ms", 0.05), ("ms", 10.0),
+                                       ("em", 1000.0)])
+def test_smooth_real_field_x_pass(shape, scheme, s1, env):
+    # real sigma1 on a mixed-radix x length: real-field mode (two real rows
+    # per complex line, half spectra in X), every field value against the
+    # oracle after three fixed iterations
+    chi = inputs.random_phase(shape, 0.3, seed=28)
+    e0 = (1, 0) if len(shape) == 2 else (1, 0, 0)
+    ref = osolver.solve(chi, s1, list(map(float, e0)), scheme, alpha=0.25, beta=4.0, tol=-1,
+                        max_iter=3, stag_window=0, div_factor=0)
+    for precision, bound in (("fp64", 1e-11), ("fp32", 2e-6)):
+        info = scfft.plan_info(chi, s1, e0, scheme, precision=precision)
+        assert info["real"] == 1 and info["x_engine"] == SMOOTH, info
+        got = scfft.solve(chi, s1, e0, scheme, precision=precision, tol=-1, max_iter=3,
+                          stag_window=0, div_factor=0)
+        assert _rel(got["E"].cpu().numpy(), ref["E"]) < bound, (precision, shape)
+        assert _rel(got["J"].cpu().numpy(), ref["J"]) < bound, (precision, shape)
+        assert abs(got["sigma_star"] - ref["sigma_star"]) / abs(ref["sigma_star"]) < bound
+
+
+def test_smooth_real_field_converged(env):
+    # converged real-field solves on a mixed-radix grid against the
+    # full-complex path (SCFFT_NO_REAL) and the oracle's sigma*
+    chi = inputs.random_phase((160, 240), 0.3, seed=29)
+    ref = osolver.solve(chi, 20.0, [1.0, 0.0], "acc_em", alpha=0.25, beta=4.0, tol=1e-12,
+                        max_iter=300)
+    out = []
+    for flag in (False, True):
+        if flag:
+            env.setenv("SCFFT_NO_REAL", "1")
+        scfft.release()
+        assert scfft.plan_info(chi, 20.0, (1, 0), "acc_em", precision="fp64")["real"] == \
+            (0 if flag else 1)
+        out.append(scfft.solve(chi, 20.0, (1, 0), "acc_em", precision="fp64", tol=1e-11,
+                               max_iter=300, fields=False))
+    a, b = out
+    assert a["status"] == 0 and a["iterations"] == b["iterations"]
+    assert abs(a["sigma_star"] - b["sigma_star"]) < 1e-12 * abs(b["sigma_star"])
+    assert abs(a["sigma_star"] - ref["sigma_star"]) < 1e-9 * abs(ref["sigma_star"])

@@ -1429,11 +1429,16 @@ cd graded_sigma0(int scheme, cd s1) {
 }
 
 // Real-field mode: every coefficient real, an x length with a real-field x
-// pass (a power of two, or a compile-time mixed-radix length) and an even
-// number of x lines (rows are transformed in pairs).
-bool real_ok(const SolveSpec& sp, int d, const int* n) {
+// pass and an even number of x lines (rows are transformed in pairs).  Power
+// of two: always.  Compile-time mixed-radix lengths: in 3D, and in 2D at
+// fp64 (measured, one accelerated iteration: 240^3 fp32 1.57 -> 0.88 ms,
+// fp64 4.08 -> 2.26 ms, 480^3 fp32 13.0 -> 7.2 ms, 960^2 fp64 125 -> 90 us;
+// but 720^2 and 960^2 fp32 60 -> 64 and 68 -> 77 us: half as many rows and
+// columns leave a single 2D solve's passes with too few workgroups).
+bool real_ok(const SolveSpec& sp, int d, const int* n, int prec) {
   if (std::getenv("SCFFT_NO_REAL")) return false;
-  const bool sm_x = !std::getenv("SCFFT_NO_SMOOTH") && smooth_lines(n[0], 8) > 0;
+  const bool sm_x = !std::getenv("SCFFT_NO_SMOOTH") && smooth_lines(n[0], 8) > 0 &&
+                    (d == 3 || prec == SCFFT_FP64);
   if (!is_p2(n[0]) && !sm_x) return false;
   const long long lines = (long long)n[1] * (d == 3 ? n[2] : 1);
   if (lines % 2) return false;
@@ -1536,7 +1541,7 @@ scfft_status scfft_solve(const scfft_problem* prob, const scfft_options* opt, sc
   const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c, &cf, prob->phase,
                    prob->density};
   rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n), &tc);
+                real_ok(sp, prob->d, prob->n, opt->precision), &tc);
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, opt->max_iter + 1);
   if (rc != SCFFT_OK) return rc;
@@ -1571,7 +1576,7 @@ scfft_status scfft_plan_info(const scfft_problem* prob, const scfft_options* opt
   const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c, &cf, prob->phase,
                    prob->density};
   rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n), &tc);
+                real_ok(sp, prob->d, prob->n, opt->precision), &tc);
   if (rc != SCFFT_OK) return rc;
   const int v[13] = {p->real ? 1 : 0, p->packed ? 1 : 0, p->kn.pitch, p->kn.nt, p->kn.xr,
                      p->kn.gr, p->gC, p->d == 3 ? p->yC : 0, p->tuned ? 1 : 0, p->xL,
@@ -1606,7 +1611,7 @@ scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_optio
   const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c[0], &cf[0], prob->phase,
                    prob->density};
   rc = get_plan(d, prob->n, opt->precision, d, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, d, prob->n), &tc);
+                real_ok(sp, d, prob->n, opt->precision), &tc);
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, opt->max_iter + 1);
   if (rc != SCFFT_OK) return rc;
@@ -1666,7 +1671,7 @@ scfft_status scfft_series_coefficients(const scfft_problem* prob, const scfft_op
   }
   const TuneCtx tc{map_kind(sp.kind, false), &c, &cf, prob->phase, nullptr};
   rc = get_plan(prob->d, prob->n, o.precision, 1, true, o.symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n), &tc);
+                real_ok(sp, prob->d, prob->n, o.precision), &tc);
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, nterms + 1);
   if (rc != SCFFT_OK) return rc;
@@ -1784,7 +1789,8 @@ scfft_status scfft_solve_batch(int nprob, const scfft_problem* probs, const scff
   std::vector<const double*> de(nprob);
   for (int i = 0; i < nprob; ++i) {
     bool real = true;
-    for (int j = 0; j < nsig; ++j) real = real && real_ok(specs[i][j], probs[i].d, probs[i].n);
+    for (int j = 0; j < nsig; ++j)
+      real = real && real_ok(specs[i][j], probs[i].d, probs[i].n, o0.precision);
     std::vector<SolveCtl> c(nsig);
     std::vector<SolveCoef> cf(nsig);
     for (int j = 0; j < nsig; ++j) {
@@ -1859,7 +1865,7 @@ scfft_status scfft_estimate_interval(const scfft_problem* prob, int iters, int s
   }
   const TuneCtx tc{MAP_LIN, &c[0], &cf[0], prob->phase, nullptr};
   rc = get_plan(prob->d, prob->n, SCFFT_FP64, 2, false, symbol, st, &p, 0,
-                real_ok(pw, prob->d, prob->n), &tc);
+                real_ok(pw, prob->d, prob->n, SCFFT_FP64), &tc);
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, iters + 2);
   if (rc != SCFFT_OK) return rc;
@@ -1917,7 +1923,7 @@ scfft_status lanczos_run(const scfft_problem* prob, int steps, int symbol, hipSt
   fill_coef(cf, pw, false, prob->d, prob->e0, (double)voxels(prob));
   const TuneCtx tc{MAP_LIN, &c, &cf, prob->phase, nullptr};
   rc = get_plan(prob->d, prob->n, SCFFT_FP64, 1, false, symbol, st, &p, 0,
-                real_ok(pw, prob->d, prob->n), &tc);
+                real_ok(pw, prob->d, prob->n, SCFFT_FP64), &tc);
   if (rc != SCFFT_OK) return rc;
   p->mk = MAP_LIN;
   SCFFT_HIP(hipMemcpyAsync(p->ctl, &c, sizeof(c), hipMemcpyHostToDevice, st));
@@ -2169,7 +2175,7 @@ scfft_status scfft_gradient(const scfft_problem* prob, const scfft_options* opt,
     const TuneCtx tc{map_kind(K_EM, prob->density != nullptr), &c0, &cf0, prob->phase,
                      prob->density};
     rc = get_plan(prob->d, prob->n, o.precision, 1, false, o.symbol, st, &p, 0,
-                  real_ok(sp, prob->d, prob->n), &tc);
+                  real_ok(sp, prob->d, prob->n, o.precision), &tc);
     if (rc == SCFFT_OK) rc = ensure_hist(p, o.max_iter + 1);
     for (int pass = 0; pass < 2 && rc == SCFFT_OK; ++pass) {
       SolveSpec s = sp;
@@ -2283,7 +2289,7 @@ scfft_status scfft_profile_passes(const scfft_problem* prob, const scfft_options
   const TuneCtx tc{map_kind(sp.kind, prob->density != nullptr), &c, &cf, prob->phase,
                    prob->density};
   rc = get_plan(prob->d, prob->n, opt->precision, 1, acc, opt->symbol, st, &p, 0,
-                real_ok(sp, prob->d, prob->n), &tc);
+                real_ok(sp, prob->d, prob->n, opt->precision), &tc);
   if (rc != SCFFT_OK) return rc;
   rc = ensure_hist(p, iters + 2);
   if (rc != SCFFT_OK) return rc;
@@ -2405,7 +2411,7 @@ scfft_status scfft_solve_noalloc(const scfft_problem* prob, const scfft_options*
   Plan p;
   p.no_alloc = true;
   const bool acc = sp.kind == K_ACC_EM || sp.kind == K_ACC_MS;
-  const bool real = real_ok(sp, prob->d, prob->n);
+  const bool real = real_ok(sp, prob->d, prob->n, opt->precision);
   // the knobs scfft_solve tuned for this configuration, if any (tuning itself
   // would allocate)
   bool tuned = false;

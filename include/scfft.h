@@ -291,9 +291,9 @@ scfft_status scfft_effective_tensor(const scfft_problem* prob, const scfft_optio
  * x-pass workgroup; with cap >= 13 also the FFT engine of [10] the x pass,
  * [11] the Gamma pass and [12] the 3D y passes (0 in 2D): 1
  * register-resident power-of-two passes, 2 compile-time mixed-radix passes
- * (of the lengths the library instantiates, 48 ... 960: x passes of
- * full-complex fields, strided passes of any field), 0 runtime-planned
- * mixed radix.
+ * (of the lengths the library instantiates, 48 ... 960: x passes and
+ * strided passes, full-complex or real-field), 0 runtime-planned mixed
+ * radix.
  * Environment overrides (SCFFT_XR, SCFFT_GR, SCFFT_LINE_C, SCFFT_YC,
  * SCFFT_PACK, SCFFT_PITCH, SCFFT_NT, SCFFT_R16=0, SCFFT_NO_SMOOTH) force
  * single choices over both. */

@@ -25,6 +25,9 @@ CASES = [
     # 3D mixed-radix passes on every axis (80-, 90- and 48-point lines)
     (lambda: inputs.random_phase((48, 90, 80), 0.3, seed=7), 3 + 2j, (1, 0, 0), "acc_em", "fp32",
      1e-6, 200),
+    # the same grid with real sigma1: real-field mode on a mixed-radix x length
+    (lambda: inputs.random_phase((48, 90, 80), 0.3, seed=8), 10.0, (0, 1, 0), "acc_em", "fp64",
+     1e-10, 200),
 ]
 
 
@@ -53,7 +56,7 @@ def _check(ref, got):
     assert len(got["sigma_history"]) == n + 1
 
 
-@pytest.mark.parametrize("order", [(0, 1), (2, 3), (0, 2), (4, 1)])
+@pytest.mark.parametrize("order", [(0, 1), (2, 3), (0, 2), (4, 1), (5, 4)])
 def test_noalloc_matches_solve_two_calls(order):
     """Two calls in a row, the second on a smaller problem."""
     for k in order:

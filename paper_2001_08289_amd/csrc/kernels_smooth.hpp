@@ -325,6 +325,29 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_r2c_kernel(
   lm.load(a, solve, comp, cbase * a.M);
   const auto wa = lm.row(rowA * N);
   const auto wb = lm.row(rowB * N);
+  // the phase maps and E_prev do not depend on the FFT: load them first
+  // when the registers allow (at most 16 fp32 / 8 fp64 points per lane)
+  constexpr bool PF = (MK == MAP_LIN || MK == MAP_ACC_EM || MK == MAP_ACC_MS) &&
+                      B0 * R0 * (int)sizeof(cx<T>) <= 128;
+  constexpr int PB = PF ? B0 : 1, PR = PF ? R0 : 1;
+  bool pha[PB][PR], phb[PB][PR];
+  T epa[PB][PR], epb[PB][PR];
+  if (PF && valid) {
+#pragma unroll
+    for (int u = 0; u < B0; ++u) {
+      const int j = lane + LW * u;
+      if (NB0 % LW == 0 || j < NB0) {
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          const unsigned int k = (unsigned int)(j + q * NB0);
+          pha[PF ? u : 0][PF ? q : 0] = wa.ph[k] != 0;
+          phb[PF ? u : 0][PF ? q : 0] = wb.ph[k] != 0;
+          epa[PF ? u : 0][PF ? q : 0] = wa.Ep[k];
+          epb[PF ? u : 0][PF ? q : 0] = wb.Ep[k];
+        }
+      }
+    }
+  }
   sm_fft<T, N>(v0, slot, tw, (T)1, lane);
   Acc acc;
 #pragma unroll
@@ -335,8 +358,13 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_r2c_kernel(
       for (int q = 0; q < R0; ++q) {
         const unsigned int k = (unsigned int)(j + q * NB0);
         const cx<T> z = slot[k];
-        const T oa = lm.apply(z.x, wa, k, acc);
-        const T ob = lm.apply(z.y, wb, k, acc);
+        const int pu = PF ? u : 0, pq = PF ? q : 0;
+        const T oa = PF ? lm.template apply_pf<false>(z.x, pha[pu][pq], epa[pu][pq], (T)0, (T)0,
+                                                      wa, k, acc)
+                        : lm.apply(z.x, wa, k, acc);
+        const T ob = PF ? lm.template apply_pf<false>(z.y, phb[pu][pq], epb[pu][pq], (T)0, (T)0,
+                                                      wb, k, acc)
+                        : lm.apply(z.y, wb, k, acc);
         v0[u][q] = mk<T>(oa, ob);
         acc_settle<false>(acc);
       }

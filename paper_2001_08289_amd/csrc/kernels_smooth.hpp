@@ -330,8 +330,13 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_r2c_kernel(
   constexpr bool PF = (MK == MAP_LIN || MK == MAP_ACC_EM || MK == MAP_ACC_MS) &&
                       B0 * R0 * (int)sizeof(cx<T>) <= 128;
   constexpr int PB = PF ? B0 : 1, PR = PF ? R0 : 1;
+  // the H'' slots of phase-1 voxels too, for up to 8 fp32 points per lane
+  constexpr bool PSL = PF && sizeof(T) == 4 && B0 * R0 <= 8;
+  constexpr bool PS = PSL && (MK == MAP_ACC_EM || MK == MAP_ACC_MS);
+  constexpr bool PT = PSL && MK == MAP_ACC_EM;
   bool pha[PB][PR], phb[PB][PR];
   T epa[PB][PR], epb[PB][PR];
+  T sa[PB][PR], sb[PB][PR], ta[PB][PR], tb[PB][PR];
   if (PF && valid) {
 #pragma unroll
     for (int u = 0; u < B0; ++u) {
@@ -340,10 +345,20 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_r2c_kernel(
 #pragma unroll
         for (int q = 0; q < R0; ++q) {
           const unsigned int k = (unsigned int)(j + q * NB0);
-          pha[PF ? u : 0][PF ? q : 0] = wa.ph[k] != 0;
-          phb[PF ? u : 0][PF ? q : 0] = wb.ph[k] != 0;
-          epa[PF ? u : 0][PF ? q : 0] = wa.Ep[k];
-          epb[PF ? u : 0][PF ? q : 0] = wb.Ep[k];
+          const int pu = PF ? u : 0, pq = PF ? q : 0;
+          pha[pu][pq] = wa.ph[k] != 0;
+          phb[pu][pq] = wb.ph[k] != 0;
+          epa[pu][pq] = wa.Ep[k];
+          epb[pu][pq] = wb.Ep[k];
+        }
+#pragma unroll
+        for (int q = 0; q < R0; ++q) {
+          const unsigned int k = (unsigned int)(j + q * NB0);
+          const int pu = PF ? u : 0, pq = PF ? q : 0;
+          sa[pu][pq] = (PS && pha[pu][pq]) ? wa.S[k] : (T)0;
+          sb[pu][pq] = (PS && phb[pu][pq]) ? wb.S[k] : (T)0;
+          ta[pu][pq] = (PT && pha[pu][pq]) ? wa.Tt[k] : (T)0;
+          tb[pu][pq] = (PT && phb[pu][pq]) ? wb.Tt[k] : (T)0;
         }
       }
     }
@@ -359,11 +374,11 @@ __global__ __launch_bounds__((64 * SmShape<T, N>::XW)) void xpass_sm_r2c_kernel(
         const unsigned int k = (unsigned int)(j + q * NB0);
         const cx<T> z = slot[k];
         const int pu = PF ? u : 0, pq = PF ? q : 0;
-        const T oa = PF ? lm.template apply_pf<false>(z.x, pha[pu][pq], epa[pu][pq], (T)0, (T)0,
-                                                      wa, k, acc)
+        const T oa = PF ? lm.template apply_pf<PSL>(z.x, pha[pu][pq], epa[pu][pq], sa[pu][pq],
+                                                    ta[pu][pq], wa, k, acc)
                         : lm.apply(z.x, wa, k, acc);
-        const T ob = PF ? lm.template apply_pf<false>(z.y, phb[pu][pq], epb[pu][pq], (T)0, (T)0,
-                                                      wb, k, acc)
+        const T ob = PF ? lm.template apply_pf<PSL>(z.y, phb[pu][pq], epb[pu][pq], sb[pu][pq],
+                                                    tb[pu][pq], wb, k, acc)
                         : lm.apply(z.y, wb, k, acc);
         v0[u][q] = mk<T>(oa, ob);
         acc_settle<false>(acc);

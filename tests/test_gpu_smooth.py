@@ -222,3 +222,39 @@ def test_smooth_real_field_converged(env):
     assert a["status"] == 0 and a["iterations"] == b["iterations"]
     assert abs(a["sigma_star"] - b["sigma_star"]) < 1e-12 * abs(b["sigma_star"])
     assert abs(a["sigma_star"] - ref["sigma_star"]) < 1e-9 * abs(ref["sigma_star"])
+
+
+def test_smooth_real_field_entry_points(env):
+    # every entry point that iterates the x pass, in real-field mode on a
+    # mixed-radix grid (96^2 fp64) against the same call on full-complex
+    # fields (SCFFT_NO_REAL)
+    chi = inputs.random_phase((96, 96), 0.3, seed=30)
+    rho = torch.tensor(inputs.density_field(96, seed=31), dtype=torch.float64, device="cuda")
+    out = []
+    for flag in (False, True):
+        if flag:
+            env.setenv("SCFFT_NO_REAL", "1")
+        else:
+            env.delenv("SCFFT_NO_REAL", raising=False)
+        scfft.release()
+        assert scfft.plan_info(chi, 20.0, (1, 0), "em", precision="fp64")["real"] == \
+            (0 if flag else 1)
+        r = {}
+        g = scfft.gradient(density=rho, sigma1=20.0, e0=(1, 0), precision="fp64", tol=1e-12,
+                           max_iter=3000)
+        r["drho"] = g["drho"].real.cpu().numpy()
+        r["dsigma1"] = complex(g["dsigma1"])
+        r["interval"] = scfft.estimate_interval(chi, iters=40)
+        r["lanczos"] = scfft.lanczos(chi, (1, 0), steps=12)
+        r["series"] = scfft.series_coefficients(chi, (1, 0), nterms=10)
+        r["tensor"] = np.array(scfft.effective_tensor(chi, 20.0, "acc_em", tol=1e-12)["tensor"])
+        out.append(r)
+    a, b = out
+    assert _rel(a["drho"], b["drho"]) < 1e-9
+    assert abs(a["dsigma1"] - b["dsigma1"]) < 1e-10 * abs(b["dsigma1"])
+    for k in ("alpha", "beta"):
+        assert abs(a["interval"][k] - b["interval"][k]) < 1e-10 * abs(b["interval"][k])
+    assert np.allclose(a["lanczos"]["a"], b["lanczos"]["a"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(a["lanczos"]["b"], b["lanczos"]["b"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(a["series"], b["series"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(a["tensor"], b["tensor"], rtol=1e-10, atol=1e-12)
